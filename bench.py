@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the D2Q9 T2S2-FDLBM step on one MI355X.
+
+Workload: Taylor-Green vortex on a 4096 x 4096 periodic grid over [0, 2pi]^2,
+U0 = 0.01, CFL = 0.9, eta = 0.01, T2S2-FDLBM1 (A = 1/2), FP64 state,
+initialised with eq 3.5 (synthetic, from the closed form).  nu = 1e-4: at
+nu = 1e-3 this grid has dt / tau = 0.46, where the scheme is unstable at
+CFL 0.9 for every eta (the oracle blows up the same way); nu = 1e-4 gives
+dt / tau = 4.6, inside the stable region, with the same work per step.
+A step is one full time step of the grid (one launch of the fused kernel).
+
+Prints one JSON line: MLUPS (lattice-node updates per second, all nodes),
+the roofline of the fused step kernel (algorithmic bytes per launch / the
+launch time measured with HIP events on the launch stream), and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+BYTES_PER_NODE = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36}
+METRIC = "D2Q9 MLUPS & % HBM peak, FP64 vs FP32/BF16-store at stated L2 error"
+KERNEL_SOURCES = ["paper_1911_12913_amd/csrc/t2s2_kernels.hip",
+                  "paper_1911_12913_amd/csrc/t2s2_internal.h",
+                  "paper_1911_12913_amd/csrc/t2s2_api.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_tgv4096.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = rec.get(storage)
+    if not entry or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def tgv_case(n, nu, cfl, eta):
+    import workloads as W
+
+    return W.tgv_case(n, n, u0=0.01, nu=nu, cfl=cfl, eta=eta)
+
+
+def gpu_leg(args, case):
+    import torch
+
+    import paper_1911_12913_amd as t2s2
+
+    torch.cuda.set_device(0)
+    ctx = t2s2.context_for_case(case, storage=args.storage, device="cuda:0")
+    ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = ctx.stream
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    ctx.step(args.steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    diag = ctx.diagnostics()
+    return ms, diag, ctx.dt
+
+
+def cpu_leg(case, steps, threads):
+    import oracle
+
+    oracle.build(force=False)
+    used = oracle.set_threads(threads)
+    t0 = time.perf_counter()
+    phi = oracle.init(case)
+    t1 = time.perf_counter()
+    oracle.run(case, phi, steps, threads=used)
+    t2 = time.perf_counter()
+    return (t2 - t1), used
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=4096, help="grid side")
+    ap.add_argument("--storage", default="f64", choices=sorted(BYTES_PER_NODE))
+    ap.add_argument("--nu", type=float, default=1e-4)
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="oracle steps timed on the host (0 = skip)")
+    ap.add_argument("--cpu-threads", type=int, default=None)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="after the timed region, one plain device copy of this many bytes "
+                         "(reference dispatch for scaling rocprofv3 memory counters)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    n, nu, cfl, eta = args.n, args.nu, 0.9, 0.01
+    case = tgv_case(n, nu, cfl, eta)
+    nodes = n * n
+    ms, diag, dt = gpu_leg(args, case)
+    if args.copy_bytes > 0:
+        import torch
+
+        a = torch.empty(args.copy_bytes, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    ms_step = ms / args.steps
+    mlups = nodes * args.steps / (ms * 1e-3) / 1e6
+    bytes_launch = BYTES_PER_NODE[args.storage] * nodes
+    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    traffic = measured_traffic(args.storage)
+
+    cpu = None
+    if args.cpu_steps > 0:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        secs, used = cpu_leg(case, args.cpu_steps, threads)
+        cpu = {"value": nodes * args.cpu_steps / secs / 1e6, "unit": "MLUPS", "cores": used,
+               "kind": "oracle",
+               "sample": f"{args.cpu_steps} FP64 oracle steps of the same {n}x{n} TGV grid "
+                         f"({secs:.1f} s, {used} OpenMP threads)"}
+
+    rec = {
+        "metric": METRIC,
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic (Taylor-Green closed form, eq 3.4/3.5 initial state)",
+        "config": {"workload": f"tgv{n}x{n}", "grid": [n, n], "domain": "[0,2pi]^2 periodic",
+                   "u0": 0.01, "nu": nu, "cfl": cfl, "eta": eta, "A": 0.5, "dt": dt,
+                   "scheme": "T2S2-FDLBM1", "storage": args.storage},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "step_kernel", "bytes_per_node": BYTES_PER_NODE[args.storage]},
+        "cpu_baseline": cpu,
+        "diagnostics_after": {k: diag[k] for k in ("kinetic_energy", "max_speed", "nonfinite")},
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,147 @@
+/*
+ * t2s2 — D2Q9 T2S2-FDLBM time step on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the finite-difference lattice Boltzmann scheme of Chen,
+ * Chai, Wang & Shi, "A finite-difference lattice Boltzmann model with
+ * second-order accuracy of time and space for incompressible flow"
+ * (arXiv 1911.12913):
+ *   - BGK collision (eq 2.4) with the D2Q9 equilibrium (eq 3.2) and the
+ *     moments of eq 3.3; Guo's force term (eq 3.12);
+ *   - the mixed central / second-order upwind gradient (eqs 2.36-2.38) on a
+ *     separable stretched Cartesian mesh (eqs 3.9, 3.11), taken in node-index
+ *     space with the metric 1/x'(i), x'(i) = (x[i+1] - x[i-1]) / 2;
+ *   - the two-stage march of Sec. 2D: half-step characteristic prediction
+ *     (eqs 2.33, 2.35, 2.51, 2.52) and full-step update (eqs 2.20, 2.23).
+ *     A = 0.5 is T2S2-FDLBM1; A = 0 is Guo's T1S2-FDLBM (Remark I).
+ *   - non-equilibrium extrapolation on wall nodes (eq 3.10); periodic axes.
+ *
+ * Conventions
+ *   - Every call returns an int status (T2S2_OK, T2S2_ERR_*).  Nothing throws
+ *     across this boundary; t2s2_last_error() returns a message for the last
+ *     failure on the calling thread.
+ *   - The library never allocates device memory.  State buffers and the
+ *     workspace are provided by the caller (device pointers) and must outlive
+ *     the context.  Host pointers are read only during the call.
+ *   - Device work is enqueued on the bound HIP stream and is asynchronous,
+ *     except where a call is marked "synchronises".
+ *   - Distributions cross the boundary as deviations from the rest state,
+ *     g_q = f~_q - w_q (w_q the D2Q9 weights), FP64, dense layout [9][ny][nx]
+ *     with x fastest.  Macroscopic fields are FP64 [ny][nx].
+ *   - Lattice speed xi = 1, c_s^2 = 1/3, relaxation time tau = nu / c_s^2.
+ */
+#ifndef T2S2_H
+#define T2S2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define T2S2_OK 0
+#define T2S2_ERR_INVALID_ARG 1
+#define T2S2_ERR_HIP 2
+#define T2S2_ERR_UNSUPPORTED 3
+#define T2S2_ERR_NONFINITE 4
+#define T2S2_ERR_NOT_BOUND 5
+
+/* Storage of the carried state g = f~ - w.  T2S2_F64 computes in FP64; the
+ * reduced forms compute in FP32 with FP64 moment sums. */
+#define T2S2_F64 0
+#define T2S2_F32_DEV 1
+#define T2S2_BF16_DEV 2
+#define T2S2_F16_DEV 3
+
+/* Number of values written by t2s2_diagnostics. */
+#define T2S2_NDIAG 6
+
+typedef struct t2s2_config {
+  double nu;            /* kinematic viscosity > 0; +INFINITY = no collision */
+  double cfl;           /* dt = cfl * (minimum node spacing) / xi (eq 3.1) */
+  double dt;            /* if > 0, overrides cfl */
+  double eta;           /* upwind weight of the mixed difference, in [0, 1] */
+  double A;             /* intermediate stage at t + A dt, in [0, 1] */
+  double force[2];      /* body-force acceleration (eq 3.12) */
+  double u_wall[4][2];  /* wall velocity: left, right, bottom, top; corner
+                           nodes take the left/right value */
+  int periodic_x;       /* 1: x periodic with period period_x; 0: walls */
+  int periodic_y;
+  double period_x;
+  double period_y;
+  int storage;          /* T2S2_F64, T2S2_F32_DEV, T2S2_BF16_DEV, T2S2_F16_DEV */
+} t2s2_config;
+
+typedef struct t2s2_ctx t2s2_ctx;
+
+/* Create a context for the mesh with node coordinates x[nx], y[ny] (host,
+ * strictly increasing; on a walled axis the first and last nodes are walls;
+ * on a periodic axis x[nx-1] - x[0] < period).  Validates nx, ny >= 5,
+ * 0 < cfl <= 1 (unless dt > 0), nu > 0, 0 <= eta <= 1, 0 <= A <= 1, and
+ * computes dt and the stencil coefficients on the host.  No device call. */
+int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y, int ny,
+                t2s2_ctx** out);
+
+/* Bytes of one state buffer: 9 * ny * pitch * sizeof(storage element);
+ * pitch = nx rounded up to a multiple of 64. */
+size_t t2s2_state_bytes(const t2s2_ctx* ctx);
+
+/* Bytes of the workspace (stencil weights, quadrature weights, reduction
+ * partials), 256-byte aligned device memory. */
+size_t t2s2_workspace_bytes(const t2s2_ctx* ctx);
+
+/* Attach two state buffers (ping-pong), the workspace and a hipStream_t
+ * (NULL = default stream).  Uploads the weight tables; synchronises. */
+int t2s2_bind(t2s2_ctx* ctx, void* state_a, void* state_b, void* workspace, void* stream);
+
+/* f~ = f^eq(rho, u) (Sec. 3), minus the non-equilibrium part of eq 3.5
+ * when grad is non-NULL: rho0 w (2 tau + dt)/(2 c_s^2) xi xi : grad u with
+ * rho0 = 1.  Device pointers: rho, ux, uy [ny][nx]; grad [4][ny][nx] =
+ * du/dx, du/dy, dv/dx, dv/dy.  Writes the current buffer. */
+int t2s2_init_macro(t2s2_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                    const double* grad);
+
+/* Load an arbitrary state g = f~ - w (device, FP64 [9][ny][nx]) into the
+ * current buffer, rounding to the storage type (nearest even). */
+int t2s2_init_distributions(t2s2_ctx* ctx, const double* g);
+
+/* Advance nsteps >= 0 time steps (Sec. 2D, eq 2.23); asynchronous. */
+int t2s2_step(t2s2_ctx* ctx, int64_t nsteps);
+
+/* Index (0 = state_a, 1 = state_b) of the buffer holding the current state. */
+int t2s2_current(const t2s2_ctx* ctx);
+
+/* Number of steps taken since the last init. */
+int64_t t2s2_steps_taken(const t2s2_ctx* ctx);
+
+/* Time step dt in use. */
+double t2s2_dt(const t2s2_ctx* ctx);
+
+/* Macroscopic fields of eq 3.3 into device arrays [ny][nx]:
+ * drho = rho - 1, ux, uy (momentum shifted by dt/2 rho F).  Any may be NULL.
+ * Asynchronous. */
+int t2s2_moments(t2s2_ctx* ctx, double* drho, double* ux, double* uy);
+
+/* Current state as FP64 deviations g = f~ - w into device memory
+ * [9][ny][nx].  Asynchronous. */
+int t2s2_read_distributions(t2s2_ctx* ctx, double* g);
+
+/* Global diagnostics of the current state, FP64, deterministic reduction
+ * (fixed block partition and order).  J = trapezoid cell measure of the
+ * separable mesh.  out[0] = sum J (rho - 1), out[1] = sum J rho |u|^2 / 2,
+ * out[2] = max |u|, out[3] = count of nodes with a non-finite population,
+ * out[4] = sum J rho ux, out[5] = sum J rho uy.  out is host memory;
+ * synchronises.  Returns T2S2_ERR_NONFINITE (after filling out) when
+ * out[3] > 0. */
+int t2s2_diagnostics(t2s2_ctx* ctx, double out[T2S2_NDIAG]);
+
+void t2s2_destroy(t2s2_ctx* ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* t2s2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* T2S2_H */

@@ -1,0 +1,235 @@
+"""MI355X D2Q9 T2S2-FDLBM step library: Python binding of libt2s2.so.
+
+Argument marshalling only.  Every step of the method runs in the HIP
+kernels behind the C-ABI declared in include/t2s2.h; PyTorch provides device
+memory and the current HIP stream.  There is no CPU fallback: without the
+built library (python -m paper_1911_12913_amd.build) or without a GPU, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libt2s2.so")
+
+OK, ERR_INVALID_ARG, ERR_HIP, ERR_UNSUPPORTED, ERR_NONFINITE, ERR_NOT_BOUND = range(6)
+F64, F32_DEV, BF16_DEV, F16_DEV = range(4)
+STORAGE = {"f64": F64, "f32": F32_DEV, "bf16": BF16_DEV, "f16": F16_DEV}
+NDIAG = 6
+DIAG_NAMES = ("mass_excess", "kinetic_energy", "max_speed", "nonfinite", "momentum_x",
+              "momentum_y")
+
+
+class T2S2Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"t2s2 error {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    """Mirror of struct t2s2_config (include/t2s2.h)."""
+
+    _fields_ = [
+        ("nu", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("A", ctypes.c_double),
+        ("force", ctypes.c_double * 2),
+        ("u_wall", (ctypes.c_double * 2) * 4),
+        ("periodic_x", ctypes.c_int),
+        ("periodic_y", ctypes.c_int),
+        ("period_x", ctypes.c_double),
+        ("period_y", ctypes.c_double),
+        ("storage", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libt2s2.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with "
+                           "`python -m paper_1911_12913_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i, d, sz, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_int64
+    sig = {
+        "t2s2_create": (i, [ctypes.POINTER(Config), vp, i, vp, i, ctypes.POINTER(vp)]),
+        "t2s2_state_bytes": (sz, [vp]),
+        "t2s2_workspace_bytes": (sz, [vp]),
+        "t2s2_bind": (i, [vp, vp, vp, vp, vp]),
+        "t2s2_init_macro": (i, [vp, vp, vp, vp, vp]),
+        "t2s2_init_distributions": (i, [vp, vp]),
+        "t2s2_step": (i, [vp, i64]),
+        "t2s2_current": (i, [vp]),
+        "t2s2_steps_taken": (i64, [vp]),
+        "t2s2_dt": (d, [vp]),
+        "t2s2_moments": (i, [vp, vp, vp, vp]),
+        "t2s2_read_distributions": (i, [vp, vp]),
+        "t2s2_diagnostics": (i, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "t2s2_destroy": (None, [vp]),
+        "t2s2_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> Sequence[str]:
+    return ("t2s2_create", "t2s2_state_bytes", "t2s2_workspace_bytes", "t2s2_bind",
+            "t2s2_init_macro", "t2s2_init_distributions", "t2s2_step", "t2s2_current",
+            "t2s2_steps_taken", "t2s2_dt", "t2s2_moments", "t2s2_read_distributions",
+            "t2s2_diagnostics", "t2s2_destroy", "t2s2_last_error")
+
+
+def _check(rc: int):
+    if rc != OK:
+        msg = _lib.t2s2_last_error()
+        raise T2S2Error(rc, msg.decode() if msg else "")
+
+
+def make_config(*, nu: float, cfl: float = 0.0, dt: float = 0.0, eta: float = 0.01,
+                A: float = 0.5, force=(0.0, 0.0), u_wall=None, periodic_x: bool = True,
+                periodic_y: bool = True, period_x: float = 0.0, period_y: float = 0.0,
+                storage="f64") -> Config:
+    cfg = Config()
+    cfg.nu = float(nu)
+    cfg.cfl = float(cfl)
+    cfg.dt = float(dt) if dt else 0.0
+    cfg.eta = float(eta)
+    cfg.A = float(A)
+    cfg.force[0], cfg.force[1] = float(force[0]), float(force[1])
+    if u_wall is not None:
+        for s in range(4):
+            cfg.u_wall[s][0] = float(u_wall[s][0])
+            cfg.u_wall[s][1] = float(u_wall[s][1])
+    cfg.periodic_x = int(bool(periodic_x))
+    cfg.periodic_y = int(bool(periodic_y))
+    cfg.period_x = float(period_x)
+    cfg.period_y = float(period_y)
+    cfg.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    return cfg
+
+
+class Context:
+    """Owns a t2s2_ctx and the torch tensors bound to it (two state buffers
+    and the workspace) on one HIP device and stream."""
+
+    def __init__(self, cfg: Config, x, y, device=None, stream=None):
+        import numpy as np
+        import torch
+
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("t2s2 needs a HIP device (torch.cuda.is_available() is False)")
+        self._torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        xs = np.ascontiguousarray(x, dtype=np.float64)
+        ys = np.ascontiguousarray(y, dtype=np.float64)
+        self.nx, self.ny = int(xs.shape[0]), int(ys.shape[0])
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        _check(lib.t2s2_create(ctypes.byref(cfg), xs.ctypes.data, self.nx, ys.ctypes.data,
+                               self.ny, ctypes.byref(h)))
+        self._h = h
+        nbytes = int(lib.t2s2_state_bytes(h))
+        wbytes = int(lib.t2s2_workspace_bytes(h))
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            # torch's caching allocator returns >= 512-byte aligned blocks
+            self.state = [torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+                          for _ in range(2)]
+            self.workspace = torch.empty(wbytes, dtype=torch.uint8, device=self.device)
+            _check(lib.t2s2_bind(h, self.state[0].data_ptr(), self.state[1].data_ptr(),
+                                 self.workspace.data_ptr(), self.stream.cuda_stream))
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.t2s2_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers
+    def _f64(self, a, shape):
+        t = self._torch
+        a = t.as_tensor(a, dtype=t.float64, device=self.device).contiguous()
+        if tuple(a.shape) != tuple(shape):
+            raise ValueError(f"expected shape {shape}, got {tuple(a.shape)}")
+        return a
+
+    @property
+    def dt(self) -> float:
+        return float(_lib.t2s2_dt(self._h))
+
+    @property
+    def steps_taken(self) -> int:
+        return int(_lib.t2s2_steps_taken(self._h))
+
+    @property
+    def current(self) -> int:
+        return int(_lib.t2s2_current(self._h))
+
+    # -- the C-ABI calls
+    def init_macro(self, rho, ux, uy, grad=None):
+        shp = (self.ny, self.nx)
+        r, u, v = self._f64(rho, shp), self._f64(ux, shp), self._f64(uy, shp)
+        g = self._f64(grad, (4,) + shp) if grad is not None else None
+        self._keep = (r, u, v, g)  # alive until the stream has consumed them
+        _check(_lib.t2s2_init_macro(self._h, r.data_ptr(), u.data_ptr(), v.data_ptr(),
+                                    g.data_ptr() if g is not None else None))
+
+    def init_distributions(self, g):
+        gd = self._f64(g, (9, self.ny, self.nx))
+        self._keep = (gd,)
+        _check(_lib.t2s2_init_distributions(self._h, gd.data_ptr()))
+
+    def step(self, n: int = 1):
+        _check(_lib.t2s2_step(self._h, int(n)))
+
+    def moments(self):
+        t = self._torch
+        out = [t.empty((self.ny, self.nx), dtype=t.float64, device=self.device) for _ in range(3)]
+        _check(_lib.t2s2_moments(self._h, *[o.data_ptr() for o in out]))
+        return tuple(out)
+
+    def read_distributions(self):
+        t = self._torch
+        g = t.empty((9, self.ny, self.nx), dtype=t.float64, device=self.device)
+        _check(_lib.t2s2_read_distributions(self._h, g.data_ptr()))
+        return g
+
+    def diagnostics(self, raise_nonfinite: bool = True) -> dict:
+        out = (ctypes.c_double * NDIAG)()
+        rc = _lib.t2s2_diagnostics(self._h, out)
+        if rc != OK and not (rc == ERR_NONFINITE and not raise_nonfinite):
+            _check(rc)
+        return dict(zip(DIAG_NAMES, list(out)))
+
+
+def context_for_case(case, storage="f64", device=None, **overrides) -> Context:
+    """Context for a workloads.Case-like object (x, y, periodic flags, nu,
+    cfl/dt, eta, A, force, u_wall)."""
+    kw = dict(nu=case.nu, cfl=case.cfl, dt=case.dt or 0.0, eta=case.eta, A=case.A,
+              force=case.force, u_wall=case.u_wall, periodic_x=case.periodic_x,
+              periodic_y=case.periodic_y, period_x=case.period_x, period_y=case.period_y,
+              storage=storage)
+    kw.update(overrides)
+    return Context(make_config(**kw), case.x, case.y, device=device)

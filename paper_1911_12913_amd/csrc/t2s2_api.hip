@@ -1,0 +1,414 @@
+// C-ABI of the t2s2 library (declared in include/t2s2.h): argument checks,
+// time step and stencil coefficients on the host, launch plan, ping-pong
+// state.  The library allocates no device memory: the caller provides the
+// two state buffers and the workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/t2s2.h"
+#include "t2s2_internal.h"
+
+using namespace t2s2;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(T2S2_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+// Metric 1/x'(i) with x'(i) = (x[i+1] - x[i-1]) / 2 (period added across a
+// periodic seam); zero on wall nodes, which are never differentiated.
+std::vector<double> metric(const std::vector<double>& c, bool per, double period) {
+  const int n = static_cast<int>(c.size());
+  std::vector<double> m(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double cm, cp;
+    if (per) {
+      cm = i == 0 ? c[n - 1] - period : c[i - 1];
+      cp = i == n - 1 ? c[0] + period : c[i + 1];
+    } else {
+      if (i == 0 || i == n - 1) continue;
+      cm = c[i - 1];
+      cp = c[i + 1];
+    }
+    m[i] = 2.0 / (cp - cm);
+  }
+  return m;
+}
+
+// Trapezoid measure of each node (diagnostics).
+std::vector<double> measure(const std::vector<double>& c, bool per, double period) {
+  const int n = static_cast<int>(c.size());
+  std::vector<double> J(n);
+  for (int i = 0; i < n; ++i) {
+    if (per) {
+      const double cm = i == 0 ? c[n - 1] - period : c[i - 1];
+      const double cp = i == n - 1 ? c[0] + period : c[i + 1];
+      J[i] = 0.5 * (cp - cm);
+    } else if (i == 0) {
+      J[i] = 0.5 * (c[1] - c[0]);
+    } else if (i == n - 1) {
+      J[i] = 0.5 * (c[n - 1] - c[n - 2]);
+    } else {
+      J[i] = 0.5 * (c[i + 1] - c[i - 1]);
+    }
+  }
+  return J;
+}
+
+// dt-scaled stencil weights of -xi_a d/dx_a per node: for each sign of the
+// velocity component, the 4 taps of the mixed difference (eqs 2.36-2.38 with
+// eta the upwind weight) times the metric.  sign > 0 taps at offsets
+// (-2,-1,0,+1), sign < 0 at (-1,0,+1,+2).  At the first interior node of a
+// walled axis the upwind point outside the domain is replaced by quadratic
+// extrapolation, which turns that upwind difference into the central one.
+std::vector<double> stencil_weights(const std::vector<double>& m, bool per, double eta,
+                                    double dt) {
+  const int n = static_cast<int>(m.size());
+  std::vector<double> w(static_cast<size_t>(n) * kWeightsPerNode, 0.0);
+  const double up_pos[kTaps] = {eta / 2.0, -(1.0 + 3.0 * eta) / 2.0, 3.0 * eta / 2.0,
+                                (1.0 - eta) / 2.0};
+  const double up_neg[kTaps] = {-(1.0 - eta) / 2.0, -3.0 * eta / 2.0, (1.0 + 3.0 * eta) / 2.0,
+                                -eta / 2.0};
+  const double cen_pos[kTaps] = {0.0, -0.5, 0.0, 0.5};
+  const double cen_neg[kTaps] = {-0.5, 0.0, 0.5, 0.0};
+  for (int i = 0; i < n; ++i) {
+    if (!per && (i == 0 || i == n - 1)) continue;
+    const double* ap = (!per && i == 1) ? cen_pos : up_pos;
+    const double* an = (!per && i == n - 2) ? cen_neg : up_neg;
+    for (int k = 0; k < kTaps; ++k) {
+      w[static_cast<size_t>(i) * kWeightsPerNode + k] = -dt * m[i] * ap[k];
+      w[static_cast<size_t>(i) * kWeightsPerNode + kTaps + k] = dt * m[i] * an[k];
+    }
+  }
+  return w;
+}
+
+bool check_axis(const double* c, int n, int per, double period, std::string& why) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(c[i])) {
+      why = "non-finite coordinate";
+      return false;
+    }
+  for (int i = 1; i < n; ++i)
+    if (!(c[i] > c[i - 1])) {
+      why = "coordinates must be strictly increasing";
+      return false;
+    }
+  if (per && !(std::isfinite(period) && period > c[n - 1] - c[0])) {
+    why = "period must exceed the coordinate span";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+struct t2s2_ctx {
+  t2s2_config cfg;
+  int nx = 0, ny = 0;
+  long long pitch = 0;
+  double dt = 0, tau = 0, omega = 0;
+  std::vector<double> wx, wy, jx, jy;
+  std::vector<float> wx32, wy32;
+  size_t off_wx = 0, off_wy = 0, off_wx32 = 0, off_wy32 = 0, off_jx = 0, off_jy = 0,
+         off_part = 0, off_res = 0, ws_bytes = 0;
+  void* state[2] = {nullptr, nullptr};
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  int cur = 0;
+  int64_t steps = 0;
+  StepParams sp{};
+  AuxParams ap{};
+  int grid = 0;
+};
+
+extern "C" {
+
+const char* t2s2_last_error(void) { return g_last_error.c_str(); }
+
+int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y, int ny,
+                t2s2_ctx** out) {
+  g_last_error.clear();
+  if (!out) return fail(T2S2_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfg || !x || !y) return fail(T2S2_ERR_INVALID_ARG, "NULL config or coordinates");
+  if (nx < 5 || ny < 5) return fail(T2S2_ERR_INVALID_ARG, "nx and ny must be >= 5");
+  if (nx > (1 << 20) || ny > (1 << 20) || static_cast<long long>(nx) * ny > (1LL << 31))
+    return fail(T2S2_ERR_INVALID_ARG, "mesh too large");
+  std::string why;
+  if (!check_axis(x, nx, cfg->periodic_x, cfg->period_x, why))
+    return fail(T2S2_ERR_INVALID_ARG, "x: " + why);
+  if (!check_axis(y, ny, cfg->periodic_y, cfg->period_y, why))
+    return fail(T2S2_ERR_INVALID_ARG, "y: " + why);
+  if (!(cfg->nu > 0.0)) return fail(T2S2_ERR_INVALID_ARG, "nu must be > 0 (or +INFINITY)");
+  if (!(cfg->dt > 0.0) && !(cfg->cfl > 0.0 && cfg->cfl <= 1.0))
+    return fail(T2S2_ERR_INVALID_ARG, "cfl must be in (0, 1] when dt <= 0");
+  if (cfg->dt > 0.0 && !std::isfinite(cfg->dt)) return fail(T2S2_ERR_INVALID_ARG, "dt not finite");
+  if (!(cfg->eta >= 0.0 && cfg->eta <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "eta not in [0,1]");
+  if (!(cfg->A >= 0.0 && cfg->A <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "A not in [0,1]");
+  if (cfg->storage < T2S2_F64 || cfg->storage > T2S2_F16_DEV)
+    return fail(T2S2_ERR_INVALID_ARG, "unknown storage");
+  if (!std::isfinite(cfg->force[0]) || !std::isfinite(cfg->force[1]))
+    return fail(T2S2_ERR_INVALID_ARG, "force not finite");
+  for (int s = 0; s < 4; ++s)
+    if (!std::isfinite(cfg->u_wall[s][0]) || !std::isfinite(cfg->u_wall[s][1]))
+      return fail(T2S2_ERR_INVALID_ARG, "wall velocity not finite");
+
+  t2s2_ctx* c = new t2s2_ctx();
+  c->cfg = *cfg;
+  c->nx = nx;
+  c->ny = ny;
+  c->pitch = (nx + 63) / 64 * 64;
+  std::vector<double> xs(x, x + nx), ys(y, y + ny);
+
+  // eq 3.1 with xi = 1 and dx = the smallest node spacing over both axes.
+  double dmin = INFINITY;
+  for (int i = 1; i < nx; ++i) dmin = std::fmin(dmin, xs[i] - xs[i - 1]);
+  for (int i = 1; i < ny; ++i) dmin = std::fmin(dmin, ys[i] - ys[i - 1]);
+  if (cfg->periodic_x) dmin = std::fmin(dmin, xs[0] + cfg->period_x - xs[nx - 1]);
+  if (cfg->periodic_y) dmin = std::fmin(dmin, ys[0] + cfg->period_y - ys[ny - 1]);
+  c->dt = cfg->dt > 0.0 ? cfg->dt : cfg->cfl * dmin;
+  c->tau = 3.0 * cfg->nu;
+  c->omega = std::isinf(cfg->nu) ? 0.0 : c->dt / c->tau;
+
+  const double A = cfg->A, w = c->omega, dt = c->dt;
+  StepParams& p = c->sp;
+  p.nx = nx;
+  p.ny = ny;
+  p.pitch = c->pitch;
+  p.plane = c->pitch * ny;
+  p.per_x = cfg->periodic_x ? 1 : 0;
+  p.per_y = cfg->periodic_y ? 1 : 0;
+  p.A = A;
+  // Closed forms of the pointwise maps in terms of w = dt / tau:
+  //   P = fbar^{+,h} = [(2 - A w) f~ + (1 + A) w f^eq + (1 + A) dt F] / (2 + w)
+  //   Q = f~^+       = [(2 - w) f~ + 2 w f^eq + 2 dt F] / (2 + w)
+  //   R = f(t*)      = [2 S + A w f^eq* + A dt F*] / (2 + A w)
+  p.cPg = (2.0 - A * w) / (2.0 + w);
+  p.cPe = (1.0 + A) * w / (2.0 + w);
+  p.cPF = (1.0 + A) * dt / (2.0 + w);
+  p.cQg = (2.0 - w) / (2.0 + w);
+  p.cQe = 2.0 * w / (2.0 + w);
+  p.cQF = 2.0 * dt / (2.0 + w);
+  p.cRs = 2.0 / (2.0 + A * w);
+  p.cRe = A * w / (2.0 + A * w);
+  p.cRF = A * dt / (2.0 + A * w);
+  p.half_dt = 0.5 * dt;
+  p.half_h = 0.5 * A * dt;
+  p.Fx = cfg->force[0];
+  p.Fy = cfg->force[1];
+  p.has_force = (cfg->force[0] != 0.0 || cfg->force[1] != 0.0) ? 1 : 0;
+  for (int s = 0; s < 4; ++s) {
+    p.uw[s][0] = cfg->u_wall[s][0];
+    p.uw[s][1] = cfg->u_wall[s][1];
+  }
+
+  c->wx = stencil_weights(metric(xs, cfg->periodic_x, cfg->period_x), cfg->periodic_x, cfg->eta, dt);
+  c->wy = stencil_weights(metric(ys, cfg->periodic_y, cfg->period_y), cfg->periodic_y, cfg->eta, dt);
+  c->wx32.assign(c->wx.begin(), c->wx.end());
+  c->wy32.assign(c->wy.begin(), c->wy.end());
+  c->jx = measure(xs, cfg->periodic_x, cfg->period_x);
+  c->jy = measure(ys, cfg->periodic_y, cfg->period_y);
+
+  // Launch plan: strips of 56 output columns; segments of rows sized so the
+  // grid roughly fills the resident-block slots (2 per CU for FP64, more for
+  // the narrower forms) without a ragged second wave.
+  p.nstrips = (nx + kStripOut - 1) / kStripOut;
+  int target = (cfg->storage == T2S2_F64) ? 512 : 1024;
+  if (const char* e = std::getenv("T2S2_TARGET_BLOCKS")) target = std::max(1, std::atoi(e));
+  int nsegs = std::max(1, target / p.nstrips);
+  nsegs = std::min(nsegs, std::max(1, ny / 16));
+  if (const char* e = std::getenv("T2S2_SEGMENTS")) nsegs = std::max(1, std::atoi(e));
+  p.seg_rows = (ny + nsegs - 1) / nsegs;
+  p.nsegs = (ny + p.seg_rows - 1) / p.seg_rows;
+  p.nblocks = p.nstrips * p.nsegs;
+  c->grid = (p.nblocks + 7) / 8 * 8;
+
+  size_t off = 0;
+  c->off_wx = off;
+  off = align256(off + c->wx.size() * sizeof(double));
+  c->off_wy = off;
+  off = align256(off + c->wy.size() * sizeof(double));
+  c->off_wx32 = off;
+  off = align256(off + c->wx32.size() * sizeof(float));
+  c->off_wy32 = off;
+  off = align256(off + c->wy32.size() * sizeof(float));
+  c->off_jx = off;
+  off = align256(off + c->jx.size() * sizeof(double));
+  c->off_jy = off;
+  off = align256(off + c->jy.size() * sizeof(double));
+  c->off_part = off;
+  off = align256(off + static_cast<size_t>(kDiagBlocks) * kDiagSlots * sizeof(double));
+  c->off_res = off;
+  off = align256(off + kDiagSlots * sizeof(double));
+  c->ws_bytes = off;
+
+  AuxParams& a = c->ap;
+  a.nx = nx;
+  a.ny = ny;
+  a.pitch = c->pitch;
+  a.plane = c->pitch * ny;
+  a.tau = c->tau;
+  a.dt = dt;
+  a.half_dt = 0.5 * dt;
+  a.Fx = cfg->force[0];
+  a.Fy = cfg->force[1];
+  *out = c;
+  return T2S2_OK;
+}
+
+size_t t2s2_state_bytes(const t2s2_ctx* c) {
+  if (!c) return 0;
+  return static_cast<size_t>(kQ) * c->ny * c->pitch * storage_bytes(c->cfg.storage);
+}
+
+size_t t2s2_workspace_bytes(const t2s2_ctx* c) { return c ? c->ws_bytes : 0; }
+
+int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* stream) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!state_a || !state_b || !workspace || state_a == state_b)
+    return fail(T2S2_ERR_INVALID_ARG, "need two distinct state buffers and a workspace");
+  if ((reinterpret_cast<uintptr_t>(state_a) | reinterpret_cast<uintptr_t>(state_b) |
+       reinterpret_cast<uintptr_t>(workspace)) & 255)
+    return fail(T2S2_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+  c->state[0] = state_a;
+  c->state[1] = state_b;
+  c->ws = static_cast<char*>(workspace);
+  c->stream = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  struct {
+    size_t off;
+    const void* src;
+    size_t bytes;
+  } up[] = {{c->off_wx, c->wx.data(), c->wx.size() * sizeof(double)},
+            {c->off_wy, c->wy.data(), c->wy.size() * sizeof(double)},
+            {c->off_wx32, c->wx32.data(), c->wx32.size() * sizeof(float)},
+            {c->off_wy32, c->wy32.data(), c->wy32.size() * sizeof(float)},
+            {c->off_jx, c->jx.data(), c->jx.size() * sizeof(double)},
+            {c->off_jy, c->jy.data(), c->jy.size() * sizeof(double)}};
+  for (auto& u : up) {
+    e = hipMemcpyAsync(c->ws + u.off, u.src, u.bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "bind: upload");
+  }
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "bind: synchronize");
+  c->sp.wx = reinterpret_cast<const double*>(c->ws + c->off_wx);
+  c->sp.wy = reinterpret_cast<const double*>(c->ws + c->off_wy);
+  c->sp.wx32 = reinterpret_cast<const float*>(c->ws + c->off_wx32);
+  c->sp.wy32 = reinterpret_cast<const float*>(c->ws + c->off_wy32);
+  c->ap.jx = reinterpret_cast<const double*>(c->ws + c->off_jx);
+  c->ap.jy = reinterpret_cast<const double*>(c->ws + c->off_jy);
+  c->bound = true;
+  c->cur = 0;
+  c->steps = 0;
+  return T2S2_OK;
+}
+
+int t2s2_init_macro(t2s2_ctx* c, const double* rho, const double* ux, const double* uy,
+                    const double* grad) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (!rho || !ux || !uy) return fail(T2S2_ERR_INVALID_ARG, "NULL field");
+  if (grad && std::isinf(c->cfg.nu))
+    return fail(T2S2_ERR_INVALID_ARG, "eq 3.5 correction needs a finite tau");
+  hipError_t e = launch_init_macro(c->cfg.storage, c->ap, c->state[c->cur], rho, ux, uy, grad,
+                                   c->stream);
+  if (e != hipSuccess) return hip_fail(e, "init_macro");
+  c->steps = 0;
+  return T2S2_OK;
+}
+
+int t2s2_init_distributions(t2s2_ctx* c, const double* g) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (!g) return fail(T2S2_ERR_INVALID_ARG, "NULL distributions");
+  hipError_t e = launch_load_dist(c->cfg.storage, c->ap, c->state[c->cur], g, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "init_distributions");
+  c->steps = 0;
+  return T2S2_OK;
+}
+
+int t2s2_step(t2s2_ctx* c, int64_t nsteps) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (nsteps < 0) return fail(T2S2_ERR_INVALID_ARG, "nsteps < 0");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    c->sp.src = c->state[c->cur];
+    c->sp.dst = c->state[1 - c->cur];
+    hipError_t e = launch_step(c->cfg.storage, c->sp, c->grid, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "step");
+    c->cur = 1 - c->cur;
+    ++c->steps;
+  }
+  return T2S2_OK;
+}
+
+int t2s2_current(const t2s2_ctx* c) { return c ? c->cur : -1; }
+
+int64_t t2s2_steps_taken(const t2s2_ctx* c) { return c ? c->steps : -1; }
+
+double t2s2_dt(const t2s2_ctx* c) { return c ? c->dt : 0.0; }
+
+int t2s2_moments(t2s2_ctx* c, double* drho, double* ux, double* uy) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  hipError_t e =
+      launch_moments(c->cfg.storage, c->ap, c->state[c->cur], drho, ux, uy, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "moments");
+  return T2S2_OK;
+}
+
+int t2s2_read_distributions(t2s2_ctx* c, double* g) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (!g) return fail(T2S2_ERR_INVALID_ARG, "NULL output");
+  hipError_t e = launch_read_dist(c->cfg.storage, c->ap, c->state[c->cur], g, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "read_distributions");
+  return T2S2_OK;
+}
+
+int t2s2_diagnostics(t2s2_ctx* c, double out[T2S2_NDIAG]) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (!out) return fail(T2S2_ERR_INVALID_ARG, "NULL output");
+  double* part = reinterpret_cast<double*>(c->ws + c->off_part);
+  double* res = reinterpret_cast<double*>(c->ws + c->off_res);
+  hipError_t e = launch_diagnostics(c->cfg.storage, c->ap, c->state[c->cur], part, res, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics");
+  double host[kDiagSlots];
+  e = hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics: copy");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics: synchronize");
+  for (int k = 0; k < T2S2_NDIAG; ++k) out[k] = host[k];
+  if (host[3] > 0.0) return fail(T2S2_ERR_NONFINITE, "non-finite populations in the state");
+  return T2S2_OK;
+}
+
+void t2s2_destroy(t2s2_ctx* c) { delete c; }
+
+}  // extern "C"

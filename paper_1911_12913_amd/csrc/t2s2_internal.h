@@ -1,0 +1,82 @@
+// Internal declarations shared by the t2s2 host code and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace t2s2 {
+
+// D2Q9 velocities in the order printed in Sec. 3 of the paper.
+constexpr int kQ = 9;
+
+// Strip geometry of the fused step: one 64-lane wave covers 64 consecutive
+// columns; the outer 4 on each side are halo (the output depends on f~ up to
+// 4 nodes away along each axis), so a strip produces 56 output columns.
+constexpr int kLanes = 64;
+constexpr int kHalo = 4;
+constexpr int kStripOut = kLanes - 2 * kHalo;
+// Rows advanced per iteration of the y-march = waves per block.
+constexpr int kRowsPerIter = 4;
+constexpr int kBlockThreads = kLanes * kRowsPerIter;
+// LDS ring depth in rows (P rows [p0-4, p0+4), R rows [p0-6, p0+2)).
+constexpr int kRing = 8;
+
+// Stencil weights per node and sign of the velocity component: 4 taps.
+// sign > 0: offsets (-2, -1, 0, +1); sign < 0: offsets (-1, 0, +1, +2).
+constexpr int kTaps = 4;
+constexpr int kWeightsPerNode = 2 * kTaps;
+
+// Storage codes (match include/t2s2.h).
+enum Storage { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3 };
+
+struct StepParams {
+  const void* src;
+  void* dst;
+  int nx, ny;
+  long long pitch;  // elements per row
+  long long plane;  // elements per population plane (ny * pitch)
+  int per_x, per_y;
+  int nstrips, nsegs, seg_rows, nblocks;
+  const double* wx;   // [nx][2][4] dt-scaled x weights (FP64)
+  const double* wy;   // [ny][2][4]
+  const float* wx32;  // same in FP32
+  const float* wy32;
+  double A;
+  double cPg, cPe, cPF;  // P = cPg g + cPe (feq - w) + cPF F
+  double cQg, cQe, cQF;  // Q = cQg g + cQe (feq - w) + cQF F
+  double cRs, cRe, cRF;  // R = cRs S + cRe (feq* - w) + cRF F*
+  double half_dt, half_h;
+  double Fx, Fy;
+  double uw[4][2];
+  int has_force;
+};
+
+struct AuxParams {
+  int nx, ny;
+  long long pitch, plane;
+  double tau, dt;       // for the eq 3.5 correction
+  double half_dt, Fx, Fy;
+  const double* jx;     // trapezoid measure [nx]
+  const double* jy;     // [ny]
+};
+
+constexpr int kDiagBlocks = 512;
+constexpr int kDiagSlots = 8;
+
+// Launchers (t2s2_kernels.hip).  Return hipError_t of the launch.
+hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s);
+hipError_t launch_init_macro(int storage, const AuxParams& a, void* state, const double* rho,
+                             const double* ux, const double* uy, const double* grad,
+                             hipStream_t s);
+hipError_t launch_load_dist(int storage, const AuxParams& a, void* state, const double* g,
+                            hipStream_t s);
+hipError_t launch_read_dist(int storage, const AuxParams& a, const void* state, double* g,
+                            hipStream_t s);
+hipError_t launch_moments(int storage, const AuxParams& a, const void* state, double* drho,
+                          double* ux, double* uy, hipStream_t s);
+hipError_t launch_diagnostics(int storage, const AuxParams& a, const void* state,
+                              double* partials, double* result, hipStream_t s);
+
+size_t storage_bytes(int storage);
+
+}  // namespace t2s2

@@ -1,0 +1,734 @@
+// HIP kernels of the D2Q9 T2S2-FDLBM step for gfx950 (wave64).
+//
+// The fused step kernel computes one full time step f~^n -> f~^{n+1} of the
+// paper's Sec. 2D sequence in a single pass over HBM:
+//   P = fbar^{+,h}(f~)                 pointwise (eqs 2.34, 2.51)
+//   Q = f~^{+}(f~)                     pointwise (eq 2.20)
+//   S = P - h xi . grad_m P            half-step characteristic (eqs 2.33, 2.35)
+//   R = f(t*) from S                   pointwise with new moments (eqs 2.32, 2.52)
+//   f~^{n+1} = Q - dt xi . grad_m R    (eq 2.23)
+// with non-equilibrium extrapolation (eq 3.10) on wall nodes: for R inside
+// the fused kernel (the stencil reads it), for the new state in a small
+// perimeter kernel that follows it.  All populations are carried as
+// deviations g = f~ - w.
+//
+// Work decomposition: a block owns a strip of 64 columns (56 outputs plus a
+// 4-column halo each side, the reach of the two chained radius-2 stencils)
+// and a segment of rows, and marches down the segment.  Each of its four
+// waves handles one row per iteration.  P and R rows live in LDS ring
+// buffers of 8 rows; Q stays in registers for one iteration.  Every value is
+// read from HBM once per strip and written once.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include "t2s2_internal.h"
+
+namespace t2s2 {
+namespace {
+
+__host__ __device__ constexpr int ex_of(int q) {
+  return (q == 1 || q == 5 || q == 8) ? 1 : ((q == 3 || q == 6 || q == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int ey_of(int q) {
+  return (q == 2 || q == 5 || q == 6) ? 1 : ((q == 4 || q == 7 || q == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr double w_of(int q) {
+  return q == 0 ? 4.0 / 9.0 : (q < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+template <typename S>
+struct Cvt;
+template <>
+struct Cvt<double> {
+  using R = double;
+  __device__ static double ld(double v) { return v; }
+  __device__ static double st(double v) { return v; }
+};
+template <>
+struct Cvt<float> {
+  using R = float;
+  __device__ static float ld(float v) { return v; }
+  __device__ static float st(float v) { return v; }
+};
+// BF16 as raw bits: widening is a 16-bit shift; narrowing rounds to nearest
+// even by adding 0x7fff plus the lowest kept bit before truncating (NaN kept
+// quiet).
+struct Bf16 {
+  unsigned short bits;
+};
+template <>
+struct Cvt<Bf16> {
+  using R = float;
+  __device__ static float ld(Bf16 v) { return __uint_as_float(static_cast<unsigned>(v.bits) << 16); }
+  __device__ static Bf16 st(float v) {
+    const unsigned u = __float_as_uint(v);
+    if (v != v) return Bf16{static_cast<unsigned short>((u >> 16) | 0x40u)};
+    return Bf16{static_cast<unsigned short>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16)};
+  }
+};
+template <>
+struct Cvt<_Float16> {
+  using R = float;
+  __device__ static float ld(_Float16 v) { return static_cast<float>(v); }
+  __device__ static _Float16 st(float v) { return static_cast<_Float16>(v); }  // RNE
+};
+
+__device__ inline int wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+__device__ inline int clampi(int i, int lo, int hi) { return i < lo ? lo : (i > hi ? hi : i); }
+
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (each squares the relative error), for the one division per node.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// f^eq_q - w_q = w_q (drho + rho X_q),  X_q = 3 e + 9/2 e^2 - 3/2 |u|^2,
+// e = xi_q . u  (eq 3.2 with c_s^2 = 1/3).
+template <typename Real>
+__device__ inline void feq_dev(double drho, double rho, double ux, double uy, Real out[kQ]) {
+  const Real d = static_cast<Real>(drho), r = static_cast<Real>(rho);
+  const Real x = static_cast<Real>(ux), y = static_cast<Real>(uy);
+  const Real uu = Real(1.5) * (x * x + y * y);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const Real e = Real(ex_of(q)) * x + Real(ey_of(q)) * y;
+    const Real X = e * (Real(3) + Real(4.5) * e) - uu;
+    out[q] = Real(w_of(q)) * (d + r * X);
+  }
+}
+
+// Guo force term (eq 3.12): F_q = (F . (xi_q - u)) f^eq_q / c_s^2.
+template <typename Real>
+__device__ inline void force_terms(double Fx, double Fy, double ux, double uy,
+                                   const Real feq[kQ], Real out[kQ]) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const Real fu = static_cast<Real>(Fx * (ex_of(q) - ux) + Fy * (ey_of(q) - uy));
+    out[q] = Real(3) * fu * (Real(w_of(q)) + feq[q]);
+  }
+}
+
+// Moment sums in FP64 in the fixed order q = 0..8.
+template <typename Real>
+__device__ inline void moment_sums(const Real a[kQ], double& s, double& jx, double& jy) {
+  s = 0.0;
+  jx = 0.0;
+  jy = 0.0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const double v = static_cast<double>(a[q]);
+    s += v;
+    if (ex_of(q) > 0) jx += v;
+    if (ex_of(q) < 0) jx -= v;
+    if (ey_of(q) > 0) jy += v;
+    if (ey_of(q) < 0) jy -= v;
+  }
+}
+
+// f^eq(rho, u_b) - f^eq(rho, u_f) (the non-equilibrium extrapolation shift
+// of eq 3.10, with rho taken at the fluid node).
+template <typename Real>
+__device__ inline void nee_shift(double rho, double uxf, double uyf, double uxb, double uyb,
+                                 Real out[kQ]) {
+  const Real r = static_cast<Real>(rho);
+  const Real xf = static_cast<Real>(uxf), yf = static_cast<Real>(uyf);
+  const Real xb = static_cast<Real>(uxb), yb = static_cast<Real>(uyb);
+  const Real uuf = Real(1.5) * (xf * xf + yf * yf), uub = Real(1.5) * (xb * xb + yb * yb);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const Real ef = Real(ex_of(q)) * xf + Real(ey_of(q)) * yf;
+    const Real eb = Real(ex_of(q)) * xb + Real(ey_of(q)) * yb;
+    const Real Xf = ef * (Real(3) + Real(4.5) * ef) - uuf;
+    const Real Xb = eb * (Real(3) + Real(4.5) * eb) - uub;
+    out[q] = Real(w_of(q)) * r * (Xb - Xf);
+  }
+}
+
+__device__ inline void wall_velocity(const StepParams& p, int c, int r, double& ub,
+                                     double& vb) {
+  int side;
+  if (!p.per_x && c == 0)
+    side = 0;
+  else if (!p.per_x && c == p.nx - 1)
+    side = 1;
+  else if (!p.per_y && r == 0)
+    side = 2;
+  else
+    side = 3;
+  ub = p.uw[side][0];
+  vb = p.uw[side][1];
+}
+
+template <typename Real>
+__device__ inline const Real* weights_x(const StepParams& p);
+template <>
+__device__ inline const double* weights_x<double>(const StepParams& p) {
+  return p.wx;
+}
+template <>
+__device__ inline const float* weights_x<float>(const StepParams& p) {
+  return p.wx32;
+}
+template <typename Real>
+__device__ inline const Real* weights_y(const StepParams& p);
+template <>
+__device__ inline const double* weights_y<double>(const StepParams& p) {
+  return p.wy;
+}
+template <>
+__device__ inline const float* weights_y<float>(const StepParams& p) {
+  return p.wy32;
+}
+
+// ---------------------------------------------------------------------------
+// Fused step.
+// ---------------------------------------------------------------------------
+// Resident waves per SIMD the register allocation must allow: the FP64 rings
+// (68 KB per block) admit two blocks per CU; the FP32 rings admit four, which
+// the plain periodic variant reaches without spilling (the wall and force
+// variants hold more state and settle for three).
+template <typename Store, bool kForce, bool kWalls>
+constexpr int kMinWaves =
+    sizeof(typename Cvt<Store>::R) == 8 ? 2 : ((kForce || kWalls) ? 3 : 4);
+
+template <typename Store, bool kForce, bool kWalls>
+__global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) void step_kernel(
+    StepParams p) {
+  using Real = typename Cvt<Store>::R;
+  __shared__ Real ringP[kRing * kQ * kLanes];       // [slot][q][lane]
+  __shared__ Real ringR[kRing * (kQ - 1) * kLanes];  // [slot][q-1][lane]
+
+  // XCD-aware tile order: the grid is a multiple of 8 and hardware deals
+  // blocks round-robin to the 8 XCDs, so block b runs on XCD b % 8.  Giving
+  // each XCD a contiguous range of tiles keeps neighbouring strips (which
+  // share 8 halo columns) in one L2.
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int L = (b % 8) * (G / 8) + b / 8;
+  if (L >= p.nblocks) return;  // whole block, before any barrier
+  const int strip = L % p.nstrips;
+  const int seg = L / p.nstrips;
+
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+  const int nx = p.nx, ny = p.ny;
+  const int x0 = strip * kStripOut;
+  const int x1 = min(x0 + kStripOut, nx);
+  const int y0 = seg * p.seg_rows;
+  const int y1 = min(y0 + p.seg_rows, ny);
+
+  for (int i = threadIdx.x; i < kRing * kQ * kLanes; i += kBlockThreads) ringP[i] = Real(0);
+  for (int i = threadIdx.x; i < kRing * (kQ - 1) * kLanes; i += kBlockThreads) ringR[i] = Real(0);
+
+  // This lane's column; loads and weights use the wrapped (periodic) or
+  // clamped (walled) column so every ring entry holds finite data.
+  const int c = x0 - kHalo + lane;
+  const int cm = p.per_x ? wrap(c, nx) : clampi(c, 0, nx - 1);
+  Real wxr[kWeightsPerNode];
+  {
+    const Real* wx = weights_x<Real>(p);
+#pragma unroll
+    for (int k = 0; k < kWeightsPerNode; ++k) wxr[k] = wx[cm * kWeightsPerNode + k];
+  }
+  const bool col_interior = p.per_x || (c >= 1 && c <= nx - 2);
+  const bool lane_r = lane >= 2 && lane < kLanes - 2;
+  const bool lane_o = lane >= kHalo && lane < kLanes - kHalo && c < x1;
+  const bool src_xl = !p.per_x && c == 1;
+  const bool src_xr = !p.per_x && c == nx - 2;
+
+  const Store* __restrict__ src = static_cast<const Store*>(p.src);
+  Store* __restrict__ dst = static_cast<Store*>(p.dst);
+  const long long plane = p.plane;
+
+  Real qold[kQ], qnew[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) qold[q] = qnew[q] = Real(0);
+
+  const int niter = (y1 - y0 + kRowsPerIter - 1) / kRowsPerIter + 2;
+
+  // Row loads run two iterations ahead in two register buffers, so two
+  // iterations of loads are in flight while the stencil phases compute.
+  Store gA[kQ], gB[kQ];
+  auto load_row = [&](int pr, Store (&gb)[kQ]) {
+    const int prm = p.per_y ? wrap(pr, ny) : clampi(pr, 0, ny - 1);
+    const long long base = static_cast<long long>(prm) * p.pitch + cm;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) gb[q] = src[q * plane + base];
+  };
+  load_row(y0 - kHalo + t, gA);
+  load_row(y0 - kHalo + kRowsPerIter + t, gB);
+  __syncthreads();
+
+  auto iteration = [&](const int it, Store (&gb)[kQ]) {
+    const int p0 = y0 - kHalo + kRowsPerIter * it;
+
+    // ---- phase 1: P (to LDS) and Q (registers) of row p0 + t.
+    {
+      const int pr = p0 + t;
+      Real g[kQ];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) g[q] = Cvt<Store>::ld(gb[q]);
+      if (it + 2 < niter) load_row(pr + 2 * kRowsPerIter, gb);
+      double s, jx, jy;
+      moment_sums(g, s, jx, jy);
+      const double rho = 1.0 + s;
+      const double ir = recip(rho);
+      const double ux = jx * ir + p.half_dt * p.Fx;
+      const double uy = jy * ir + p.half_dt * p.Fy;
+      Real feq[kQ];
+      feq_dev(s, rho, ux, uy, feq);
+      Real F[kQ];
+      if (kForce) force_terms(p.Fx, p.Fy, ux, uy, feq, F);
+      const Real cPg = static_cast<Real>(p.cPg), cPe = static_cast<Real>(p.cPe);
+      const Real cQg = static_cast<Real>(p.cQg), cQe = static_cast<Real>(p.cQe);
+      Real* slotP = ringP + (pr & (kRing - 1)) * kQ * kLanes;
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        Real Pq = cPg * g[q] + cPe * feq[q];
+        Real Qq = cQg * g[q] + cQe * feq[q];
+        if (kForce) {
+          Pq += static_cast<Real>(p.cPF) * F[q];
+          Qq += static_cast<Real>(p.cQF) * F[q];
+        }
+        slotP[q * kLanes + lane] = Pq;
+        qnew[q] = Qq;
+      }
+    }
+    __syncthreads();
+
+    // ---- phase 2: S and R of row p0 - 2 + t (interior nodes), R to LDS.
+    {
+      const int r = p0 - 2 + t;
+      const bool row_ok =
+          r >= y0 - 2 && r < y1 + 2 && (p.per_y || (r >= 1 && r <= ny - 2));
+      if (row_ok && lane_r && col_interior) {
+        const int rm = p.per_y ? wrap(r, ny) : r;
+        const Real* wy = weights_y<Real>(p) + rm * kWeightsPerNode;
+        Real wyr[kWeightsPerNode];
+#pragma unroll
+        for (int k = 0; k < kWeightsPerNode; ++k) wyr[k] = wy[k];
+        // One base pointer per ring row (rows r-2 .. r+2) at this lane; every
+        // tap is then a compile-time offset (q plane, +-lane) of one of them.
+        // Only lanes 2..61 get here, so lane +- 2 stays inside the row.
+        const Real* rb[5];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) rb[o] = ringP + ((r + o - 2) & (kRing - 1)) * kQ * kLanes + lane;
+        const Real A = static_cast<Real>(p.A);
+        Real S[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          const Real center = rb[2][q * kLanes];
+          Real acc = Real(0);
+          if (ex_of(q) != 0) {
+            const int sx = ex_of(q) > 0 ? 0 : 1;
+#pragma unroll
+            for (int k = 0; k < kTaps; ++k)
+              acc += wxr[sx * kTaps + k] * rb[2][q * kLanes + k + sx - 2];
+          }
+          if (ey_of(q) != 0) {
+            const int sy = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+            for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][q * kLanes];
+          }
+          S[q] = center + A * acc;
+        }
+        const int slr = (r & (kRing - 1));
+        double s, jx, jy;
+        moment_sums(S, s, jx, jy);
+        const double rho = 1.0 + s;
+        const double ir = recip(rho);
+        const double ux = jx * ir + p.half_h * p.Fx;
+        const double uy = jy * ir + p.half_h * p.Fy;
+        Real feq[kQ];
+        feq_dev(s, rho, ux, uy, feq);
+        Real F[kQ];
+        if (kForce) force_terms(p.Fx, p.Fy, ux, uy, feq, F);
+        const Real cRs = static_cast<Real>(p.cRs), cRe = static_cast<Real>(p.cRe);
+        Real R[kQ];
+        R[0] = Real(0);
+        Real* slotR = ringR + slr * (kQ - 1) * kLanes;
+#pragma unroll
+        for (int q = 1; q < kQ; ++q) {
+          Real Rq = cRs * S[q] + cRe * feq[q];
+          if (kForce) Rq += static_cast<Real>(p.cRF) * F[q];
+          R[q] = Rq;
+          slotR[(q - 1) * kLanes + lane] = Rq;
+        }
+        // Wall nodes whose nearest interior node is this one (eq 3.10 on
+        // f(t*); corners take the diagonal neighbour).  Physical f carries
+        // no force shift: u_f = sum xi R / rho = u*.
+        const bool src_yb = !p.per_y && r == 1;
+        const bool src_yt = !p.per_y && r == ny - 2;
+        if (kWalls && (src_xl || src_xr || src_yb || src_yt)) {
+          for (int dy = -1; dy <= 1; ++dy) {
+            if ((dy == -1 && !src_yb) || (dy == 1 && !src_yt)) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+              if ((dx == -1 && !src_xl) || (dx == 1 && !src_xr)) continue;
+              if (dx == 0 && dy == 0) continue;
+              double ub, vb;
+              wall_velocity(p, c + dx, r + dy, ub, vb);
+              Real sh[kQ];
+              nee_shift(rho, ux, uy, ub, vb, sh);
+              Real* slotW = ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
+#pragma unroll
+              for (int q = 1; q < kQ; ++q) slotW[(q - 1) * kLanes + lane + dx] = R[q] + sh[q];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- phase 3: f~^{n+1} of row p0 - 4 + t.
+    {
+      const int o = p0 - 4 + t;
+      const bool row_ok = o >= y0 && o < y1 && (p.per_y || (o >= 1 && o <= ny - 2));
+      if (row_ok && lane_o && col_interior) {
+        const Real* wy = weights_y<Real>(p) + o * kWeightsPerNode;
+        Real wyr[kWeightsPerNode];
+#pragma unroll
+        for (int k = 0; k < kWeightsPerNode; ++k) wyr[k] = wy[k];
+        // Lanes 4..59 only: lane +- 2 stays inside the row.
+        const Real* rb[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+          rb[k] = ringR + ((o + k - 2) & (kRing - 1)) * (kQ - 1) * kLanes + lane;
+        Real out[kQ];
+        out[0] = qold[0];
+#pragma unroll
+        for (int q = 1; q < kQ; ++q) {
+          const int pq = (q - 1) * kLanes;
+          Real acc = qold[q];
+          if (ex_of(q) != 0) {
+            const int sx = ex_of(q) > 0 ? 0 : 1;
+#pragma unroll
+            for (int k = 0; k < kTaps; ++k) acc += wxr[sx * kTaps + k] * rb[2][pq + k + sx - 2];
+          }
+          if (ey_of(q) != 0) {
+            const int sy = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+            for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][pq];
+          }
+          out[q] = acc;
+        }
+        const long long base = static_cast<long long>(o) * p.pitch + c;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) dst[q * plane + base] = Cvt<Store>::st(out[q]);
+
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) qold[q] = qnew[q];
+  };
+
+  for (int it = 0; it < niter; it += 2) {
+    iteration(it, gA);
+    if (it + 1 < niter) iteration(it + 1, gB);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wall nodes of the new state (eq 3.10): f~_b = f~_f + f^eq(rho_f, u_b) -
+// f^eq(rho_f, u_f) from the nearest interior node f (diagonal at corners;
+// x-walls own the corners).  Runs after the fused step on walled domains.
+// ---------------------------------------------------------------------------
+template <typename Store>
+__global__ __launch_bounds__(256) void wall_fixup_kernel(StepParams p) {
+  using Real = typename Cvt<Store>::R;
+  Store* __restrict__ st = static_cast<Store*>(p.dst);
+  const int nx = p.nx, ny = p.ny;
+  // Perimeter enumeration: bottom row, top row, left column, right column;
+  // the columns skip the rows that the row lists already cover.
+  const int nrow = p.per_y ? 0 : nx;
+  const int ncol = p.per_x ? 0 : (p.per_y ? ny : ny - 2);
+  const int total = 2 * nrow + 2 * ncol;
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < total; k += 256 * gridDim.x) {
+    int i, j;
+    if (k < nrow) {
+      i = k;
+      j = 0;
+    } else if (k < 2 * nrow) {
+      i = k - nrow;
+      j = ny - 1;
+    } else if (k < 2 * nrow + ncol) {
+      i = 0;
+      j = (k - 2 * nrow) + (p.per_y ? 0 : 1);
+    } else {
+      i = nx - 1;
+      j = (k - 2 * nrow - ncol) + (p.per_y ? 0 : 1);
+    }
+    const int fi = p.per_x ? i : clampi(i, 1, nx - 2);
+    const int fj = p.per_y ? j : clampi(j, 1, ny - 2);
+    const long long fb = static_cast<long long>(fj) * p.pitch + fi;
+    Real v[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(st[q * p.plane + fb]);
+    double s, jx, jy;
+    moment_sums(v, s, jx, jy);
+    const double rho = 1.0 + s;
+    const double ir = recip(rho);
+    const double ux = jx * ir + p.half_dt * p.Fx;
+    const double uy = jy * ir + p.half_dt * p.Fy;
+    double ub, vb;
+    wall_velocity(p, i, j, ub, vb);
+    Real sh[kQ];
+    nee_shift(rho, ux, uy, ub, vb, sh);
+    const long long wb = static_cast<long long>(j) * p.pitch + i;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) st[q * p.plane + wb] = Cvt<Store>::st(v[q] + sh[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Auxiliary kernels: node-parallel, grid-stride.
+// ---------------------------------------------------------------------------
+template <typename Store>
+__global__ __launch_bounds__(256) void init_macro_kernel(AuxParams a, Store* state,
+                                                         const double* rho, const double* ux,
+                                                         const double* uy, const double* grad) {
+  const long long n = static_cast<long long>(a.nx) * a.ny;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    const int x = static_cast<int>(i % a.nx), y = static_cast<int>(i / a.nx);
+    const double r = rho[i];
+    double feq[kQ];
+    feq_dev<double>(r - 1.0, r, ux[i], uy[i], feq);
+    if (grad) {
+      // eq 3.5 with rho0 = 1: rho0 w (2 tau + dt)/(2 c_s^2) xi_a xi_b d_a u_b
+      const double dudx = grad[i], dudy = grad[n + i], dvdx = grad[2 * n + i],
+                   dvdy = grad[3 * n + i];
+      const double k = (2.0 * a.tau + a.dt) * 1.5;
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const double cx = ex_of(q), cy = ey_of(q);
+        const double contr = cx * cx * dudx + cx * cy * (dudy + dvdx) + cy * cy * dvdy;
+        feq[q] -= w_of(q) * k * contr;
+      }
+    }
+    const long long base = static_cast<long long>(y) * a.pitch + x;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) state[q * a.plane + base] = Cvt<Store>::st(feq[q]);
+  }
+}
+
+template <typename Store>
+__global__ __launch_bounds__(256) void load_dist_kernel(AuxParams a, Store* state,
+                                                        const double* g) {
+  const long long n = static_cast<long long>(a.nx) * a.ny;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n * kQ; i += 256LL * gridDim.x) {
+    const long long q = i / n, j = i % n;
+    const int x = static_cast<int>(j % a.nx), y = static_cast<int>(j / a.nx);
+    state[q * a.plane + static_cast<long long>(y) * a.pitch + x] =
+        Cvt<Store>::st(static_cast<typename Cvt<Store>::R>(g[i]));
+  }
+}
+
+template <typename Store>
+__global__ __launch_bounds__(256) void read_dist_kernel(AuxParams a, const Store* state,
+                                                        double* g) {
+  const long long n = static_cast<long long>(a.nx) * a.ny;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n * kQ; i += 256LL * gridDim.x) {
+    const long long q = i / n, j = i % n;
+    const int x = static_cast<int>(j % a.nx), y = static_cast<int>(j / a.nx);
+    g[i] = static_cast<double>(
+        Cvt<Store>::ld(state[q * a.plane + static_cast<long long>(y) * a.pitch + x]));
+  }
+}
+
+template <typename Store>
+__device__ inline void node_moments(const AuxParams& a, const Store* state, int x, int y,
+                                    double& s, double& ux, double& uy, bool& finite) {
+  const long long base = static_cast<long long>(y) * a.pitch + x;
+  double v[kQ];
+  finite = true;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    v[q] = static_cast<double>(Cvt<Store>::ld(state[q * a.plane + base]));
+    finite = finite && isfinite(v[q]);
+  }
+  double jx, jy;
+  moment_sums(v, s, jx, jy);
+  const double rho = 1.0 + s;
+  ux = jx / rho + a.half_dt * a.Fx;
+  uy = jy / rho + a.half_dt * a.Fy;
+}
+
+template <typename Store>
+__global__ __launch_bounds__(256) void moments_kernel(AuxParams a, const Store* state,
+                                                      double* drho, double* ux, double* uy) {
+  const long long n = static_cast<long long>(a.nx) * a.ny;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    const int x = static_cast<int>(i % a.nx), y = static_cast<int>(i / a.nx);
+    double s, u, v;
+    bool fin;
+    node_moments(a, state, x, y, s, u, v, fin);
+    if (drho) drho[i] = s;
+    if (ux) ux[i] = u;
+    if (uy) uy[i] = v;
+  }
+}
+
+// Deterministic two-pass reduction: fixed grid of kDiagBlocks blocks, each
+// thread accumulates a fixed grid-stride subset, blocks reduce through an
+// LDS tree, one final block reduces the partials in block order.
+template <typename Store>
+__global__ __launch_bounds__(256) void diag_partial_kernel(AuxParams a, const Store* state,
+                                                           double* partials) {
+  __shared__ double red[kDiagSlots][256];
+  double acc[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const long long n = static_cast<long long>(a.nx) * a.ny;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    const int x = static_cast<int>(i % a.nx), y = static_cast<int>(i / a.nx);
+    double s, u, v;
+    bool fin;
+    node_moments(a, state, x, y, s, u, v, fin);
+    const double J = a.jx[x] * a.jy[y];
+    const double rho = 1.0 + s;
+    if (fin) {
+      acc[0] += J * s;
+      acc[1] += J * rho * 0.5 * (u * u + v * v);
+      acc[2] = fmax(acc[2], sqrt(u * u + v * v));
+      acc[4] += J * rho * u;
+      acc[5] += J * rho * v;
+    } else {
+      acc[3] += 1.0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kDiagSlots; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < kDiagSlots; ++k) {
+        if (k == 2)
+          red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        else
+          red[k][threadIdx.x] += red[k][threadIdx.x + w];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kDiagSlots) partials[blockIdx.x * kDiagSlots + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void diag_final_kernel(const double* partials, int nblocks,
+                                                        double* result) {
+  const int k = threadIdx.x;
+  if (k < kDiagSlots) {
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+      const double v = partials[b * kDiagSlots + k];
+      acc = (k == 2) ? fmax(acc, v) : acc + v;
+    }
+    result[k] = acc;
+  }
+}
+
+template <typename Store>
+hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
+  const dim3 g(grid), b(kBlockThreads);
+  const bool walls = !p.per_x || !p.per_y;
+  if (p.has_force) {
+    if (walls)
+      hipLaunchKernelGGL((step_kernel<Store, true, true>), g, b, 0, s, p);
+    else
+      hipLaunchKernelGGL((step_kernel<Store, true, false>), g, b, 0, s, p);
+  } else {
+    if (walls)
+      hipLaunchKernelGGL((step_kernel<Store, false, true>), g, b, 0, s, p);
+    else
+      hipLaunchKernelGGL((step_kernel<Store, false, false>), g, b, 0, s, p);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !walls) return e;
+  const int perim = 2 * (p.nx + p.ny);
+  hipLaunchKernelGGL(wall_fixup_kernel<Store>, dim3((perim + 255) / 256), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+int aux_grid(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return static_cast<int>(g);
+}
+
+}  // namespace
+
+size_t storage_bytes(int storage) {
+  switch (storage) {
+    case kF64: return 8;
+    case kF32: return 4;
+    case kBF16: return 2;
+    case kF16: return 2;
+    default: return 0;
+  }
+}
+
+#define T2S2_DISPATCH(storage, CALL)                                  \
+  switch (storage) {                                                  \
+    case kF64: { using Store = double; CALL; } break;                 \
+    case kF32: { using Store = float; CALL; } break;                  \
+    case kBF16: { using Store = Bf16; CALL; } break;                  \
+    case kF16: { using Store = _Float16; CALL; } break;               \
+    default: return hipErrorInvalidValue;                             \
+  }
+
+hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s) {
+  T2S2_DISPATCH(storage, return launch_step_t<Store>(p, grid, s));
+  return hipSuccess;
+}
+
+hipError_t launch_init_macro(int storage, const AuxParams& a, void* state, const double* rho,
+                             const double* ux, const double* uy, const double* grad,
+                             hipStream_t s) {
+  const int grid = aux_grid(static_cast<long long>(a.nx) * a.ny);
+  T2S2_DISPATCH(storage,
+                hipLaunchKernelGGL(init_macro_kernel<Store>, dim3(grid), dim3(256), 0, s, a,
+                                   static_cast<Store*>(state), rho, ux, uy, grad));
+  return hipGetLastError();
+}
+
+hipError_t launch_load_dist(int storage, const AuxParams& a, void* state, const double* g,
+                            hipStream_t s) {
+  const int grid = aux_grid(static_cast<long long>(a.nx) * a.ny * kQ);
+  T2S2_DISPATCH(storage, hipLaunchKernelGGL(load_dist_kernel<Store>, dim3(grid), dim3(256), 0,
+                                            s, a, static_cast<Store*>(state), g));
+  return hipGetLastError();
+}
+
+hipError_t launch_read_dist(int storage, const AuxParams& a, const void* state, double* g,
+                            hipStream_t s) {
+  const int grid = aux_grid(static_cast<long long>(a.nx) * a.ny * kQ);
+  T2S2_DISPATCH(storage, hipLaunchKernelGGL(read_dist_kernel<Store>, dim3(grid), dim3(256), 0,
+                                            s, a, static_cast<const Store*>(state), g));
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int storage, const AuxParams& a, const void* state, double* drho,
+                          double* ux, double* uy, hipStream_t s) {
+  const int grid = aux_grid(static_cast<long long>(a.nx) * a.ny);
+  T2S2_DISPATCH(storage, hipLaunchKernelGGL(moments_kernel<Store>, dim3(grid), dim3(256), 0, s,
+                                            a, static_cast<const Store*>(state), drho, ux, uy));
+  return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(int storage, const AuxParams& a, const void* state,
+                              double* partials, double* result, hipStream_t s) {
+  T2S2_DISPATCH(storage,
+                hipLaunchKernelGGL(diag_partial_kernel<Store>, dim3(kDiagBlocks), dim3(256), 0,
+                                   s, a, static_cast<const Store*>(state), partials));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, kDiagBlocks, result);
+  return hipGetLastError();
+}
+
+}  // namespace t2s2

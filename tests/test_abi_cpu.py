@@ -1,0 +1,107 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+that include/t2s2.h declares, and t2s2_create validates its arguments (it
+makes no device call)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1911_12913_amd as t2s2
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "t2s2.h")).read()
+    return sorted(set(re.findall(r"\b(t2s2_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(t2s2.exported_symbols())
+
+
+def test_library_exports_every_declared_symbol():
+    lib = t2s2.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_config_struct_layout():
+    # 5 doubles, force[2], u_wall[4][2], 2 ints, 2 doubles, 1 int (+ padding)
+    assert ctypes.sizeof(t2s2.Config) == 8 * 5 + 16 + 64 + 8 + 16 + 8
+
+
+def _create(cfg, x, y):
+    lib = t2s2.load_library()
+    h = ctypes.c_void_p()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    rc = lib.t2s2_create(ctypes.byref(cfg), x.ctypes.data, x.shape[0], y.ctypes.data,
+                         y.shape[0], ctypes.byref(h))
+    return rc, h
+
+
+def _good_cfg(**kw):
+    base = dict(nu=0.01, cfl=0.5, eta=0.01, periodic_x=True, periodic_y=True,
+                period_x=2 * math.pi, period_y=2 * math.pi)
+    base.update(kw)
+    return t2s2.make_config(**base)
+
+
+def _axis(n):
+    return np.arange(n) * (2 * math.pi / n)
+
+
+def test_create_valid_and_sizes():
+    lib = t2s2.load_library()
+    rc, h = _create(_good_cfg(), _axis(100), _axis(40))
+    assert rc == t2s2.OK
+    assert lib.t2s2_state_bytes(h) == 9 * 40 * 128 * 8
+    assert lib.t2s2_workspace_bytes(h) > 0
+    assert lib.t2s2_dt(h) == pytest.approx(0.5 * 2 * math.pi / 100, rel=1e-15)
+    lib.t2s2_destroy(h)
+    rc, h = _create(_good_cfg(storage="bf16"), _axis(100), _axis(40))
+    assert rc == t2s2.OK and lib.t2s2_state_bytes(h) == 9 * 40 * 128 * 2
+    lib.t2s2_destroy(h)
+
+
+@pytest.mark.parametrize("kw,x,y", [
+    (dict(), _axis(4), _axis(40)),                       # n < 5
+    (dict(cfl=0.0), _axis(10), _axis(10)),               # cfl <= 0
+    (dict(cfl=1.5), _axis(10), _axis(10)),               # cfl > 1
+    (dict(nu=0.0), _axis(10), _axis(10)),                # nu <= 0
+    (dict(nu=float("nan")), _axis(10), _axis(10)),
+    (dict(eta=1.5), _axis(10), _axis(10)),
+    (dict(A=-0.1), _axis(10), _axis(10)),
+    (dict(storage=7), _axis(10), _axis(10)),
+    (dict(), _axis(10)[::-1].copy(), _axis(10)),          # not increasing
+    (dict(period_x=1.0), _axis(10), _axis(10)),          # period too short
+    (dict(force=(float("inf"), 0.0)), _axis(10), _axis(10)),
+])
+def test_create_rejects_bad_arguments(kw, x, y):
+    rc, h = _create(_good_cfg(**kw), x, y)
+    assert rc == t2s2.ERR_INVALID_ARG
+    assert not h.value
+    assert len(t2s2.load_library().t2s2_last_error()) > 0
+
+
+def test_calls_on_unbound_context_fail_without_device():
+    lib = t2s2.load_library()
+    rc, h = _create(_good_cfg(), _axis(20), _axis(20))
+    assert rc == t2s2.OK
+    assert lib.t2s2_step(h, 1) == t2s2.ERR_NOT_BOUND
+    assert lib.t2s2_init_distributions(h, None) == t2s2.ERR_NOT_BOUND
+    assert lib.t2s2_moments(h, None, None, None) == t2s2.ERR_NOT_BOUND
+    assert lib.t2s2_bind(h, None, None, None, None) == t2s2.ERR_INVALID_ARG
+    assert lib.t2s2_step(None, 1) == t2s2.ERR_INVALID_ARG
+    lib.t2s2_destroy(h)
+
+
+def test_infinite_nu_is_collisionless():
+    lib = t2s2.load_library()
+    rc, h = _create(_good_cfg(nu=math.inf), _axis(20), _axis(20))
+    assert rc == t2s2.OK
+    lib.t2s2_destroy(h)
