@@ -60,6 +60,12 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it with "
                            "`python -m paper_1911_12913_amd.build`")
+    # Load torch's HIP runtime first so the library binds to the same one
+    # (two HIP runtimes in one process do not share devices or memory).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i, d, sz, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_int64
     sig = {

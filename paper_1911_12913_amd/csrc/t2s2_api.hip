@@ -227,19 +227,11 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   c->jx = measure(xs, cfg->periodic_x, cfg->period_x);
   c->jy = measure(ys, cfg->periodic_y, cfg->period_y);
 
-  // Launch plan: strips of 56 output columns; segments of rows sized so the
-  // grid roughly fills the resident-block slots (2 per CU for FP64, more for
-  // the narrower forms) without a ragged second wave.
+  // Launch plan: strips of kStripOut output columns; the block count is set
+  // at bind time from the device's CU count and the kernel's occupancy.
   p.nstrips = (nx + kStripOut - 1) / kStripOut;
-  int target = (cfg->storage == T2S2_F64) ? 512 : 1024;
-  if (const char* e = std::getenv("T2S2_TARGET_BLOCKS")) target = std::max(1, std::atoi(e));
-  int nsegs = std::max(1, target / p.nstrips);
-  nsegs = std::min(nsegs, std::max(1, ny / 16));
-  if (const char* e = std::getenv("T2S2_SEGMENTS")) nsegs = std::max(1, std::atoi(e));
-  p.seg_rows = (ny + nsegs - 1) / nsegs;
-  p.nsegs = (ny + p.seg_rows - 1) / p.seg_rows;
-  p.nblocks = p.nstrips * p.nsegs;
-  c->grid = (p.nblocks + 7) / 8 * 8;
+  p.nblocks = 8;
+  c->grid = 8;
 
   size_t off = 0;
   c->off_wx = off;
@@ -316,6 +308,24 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   c->sp.wy32 = reinterpret_cast<const float*>(c->ws + c->off_wy32);
   c->ap.jx = reinterpret_cast<const double*>(c->ws + c->off_jx);
   c->ap.jy = reinterpret_cast<const double*>(c->ws + c->off_jy);
+  // One block per resident slot (CUs x blocks per CU), so every block runs
+  // in a single wave of the grid with an equal share of the strip-rows;
+  // fewer on small meshes (at least 16 strip-rows per block).  A multiple of
+  // 8 for the XCD-aware block order.
+  int dev = 0, cus = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "bind: device query");
+  const bool walls = !c->sp.per_x || !c->sp.per_y;
+  int per_cu = step_blocks_per_cu(c->cfg.storage, c->sp.has_force != 0, walls);
+  if (per_cu < 1) return fail(T2S2_ERR_HIP, "bind: step kernel cannot be resident");
+  const long long rows = static_cast<long long>(c->sp.nstrips) * c->ny;
+  long long nb = std::min<long long>(static_cast<long long>(cus) * per_cu, rows / 16);
+  if (const char* env = std::getenv("T2S2_BLOCKS")) nb = std::atoll(env);
+  nb = std::max<long long>(8, nb / 8 * 8);
+  nb = std::min<long long>(nb, std::max<long long>(8, rows / 8 * 8));
+  c->sp.nblocks = static_cast<int>(nb);
+  c->grid = static_cast<int>(nb);
   c->bound = true;
   c->cur = 0;
   c->steps = 0;

@@ -36,7 +36,8 @@ struct StepParams {
   long long pitch;  // elements per row
   long long plane;  // elements per population plane (ny * pitch)
   int per_x, per_y;
-  int nstrips, nsegs, seg_rows, nblocks;
+  int nstrips;  // strips of kStripOut output columns
+  int nblocks;  // equal ranges of the nstrips * ny strip-rows, one per block
   const double* wx;   // [nx][2][4] dt-scaled x weights (FP64)
   const double* wy;   // [ny][2][4]
   const float* wx32;  // same in FP32
@@ -65,6 +66,8 @@ constexpr int kDiagSlots = 8;
 
 // Launchers (t2s2_kernels.hip).  Return hipError_t of the launch.
 hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s);
+// Resident step-kernel blocks per CU for this variant (-1 on error).
+int step_blocks_per_cu(int storage, bool force, bool walls);
 hipError_t launch_init_macro(int storage, const AuxParams& a, void* state, const double* rho,
                              const double* ux, const double* uy, const double* grad,
                              hipStream_t s);

@@ -21,6 +21,8 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "t2s2_internal.h"
 
 namespace t2s2 {
@@ -190,13 +192,70 @@ __device__ inline const float* weights_y<float>(const StepParams& p) {
 // ---------------------------------------------------------------------------
 // Fused step.
 // ---------------------------------------------------------------------------
+// The row weights are the same for the whole wave: read them through the
+// constant address space at a wave-uniform index so they become scalar loads
+// (counted by lgkmcnt).  A vector load here would be waited for with the
+// in-order vmcnt counter and so drain the row prefetches in flight.
+template <typename Real>
+__device__ inline void row_weights(const Real* table, int row, Real out[kWeightsPerNode]) {
+  using CPtr = const __attribute__((address_space(4))) Real*;
+  const int r = __builtin_amdgcn_readfirstlane(row);
+  CPtr w = (CPtr)(table) + r * kWeightsPerNode;
+#pragma unroll
+  for (int k = 0; k < kWeightsPerNode; ++k) out[k] = w[k];
+}
+
+// Value of the neighbouring lane l-1 (from_below) or l+1 (from_above) of a
+// wave64, through DPP wave shifts (two 32-bit moves for a double).  Every
+// lane of the wave must hold a defined value; the edge lanes receive 0.
+__device__ inline double from_below(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double from_above(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float from_below(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ inline float from_above(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// sum_k w[k] v(lane + offset_k) for the 4 taps of the mixed difference
+// along x: offsets (-2,-1,0,+1) for a positive velocity component (sx = 0),
+// (-1,0,+1,+2) for a negative one (sx = 1); the neighbours come from the
+// centre values of the other lanes.
+template <int sx, typename Real>
+__device__ inline Real x_taps(const Real* w, Real centre, Real acc) {
+  const Real m1 = from_below(centre), p1 = from_above(centre);
+  if (sx == 0) {
+    const Real m2 = from_below(m1);
+    acc += w[0] * m2;
+    acc += w[1] * m1;
+    acc += w[2] * centre;
+    acc += w[3] * p1;
+  } else {
+    const Real p2 = from_above(p1);
+    acc += w[4] * m1;
+    acc += w[5] * centre;
+    acc += w[6] * p1;
+    acc += w[7] * p2;
+  }
+  return acc;
+}
+
 // Resident waves per SIMD the register allocation must allow: the FP64 rings
 // (68 KB per block) admit two blocks per CU; the FP32 rings admit four, which
-// the plain periodic variant reaches without spilling (the wall and force
-// variants hold more state and settle for three).
+// the plain periodic FP32 / FP16 variants reach without spilling (the wall
+// and force variants, and BF16 with its conversions, settle for three).
 template <typename Store, bool kForce, bool kWalls>
-constexpr int kMinWaves =
-    sizeof(typename Cvt<Store>::R) == 8 ? 2 : ((kForce || kWalls) ? 3 : 4);
+constexpr int kMinWaves = sizeof(typename Cvt<Store>::R) == 8
+                              ? 2
+                              : ((kForce || kWalls || std::is_same<Store, Bf16>::value) ? 3 : 4);
 
 template <typename Store, bool kForce, bool kWalls>
 __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) void step_kernel(
@@ -205,232 +264,240 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
   __shared__ Real ringP[kRing * kQ * kLanes];       // [slot][q][lane]
   __shared__ Real ringR[kRing * (kQ - 1) * kLanes];  // [slot][q-1][lane]
 
-  // XCD-aware tile order: the grid is a multiple of 8 and hardware deals
-  // blocks round-robin to the 8 XCDs, so block b runs on XCD b % 8.  Giving
-  // each XCD a contiguous range of tiles keeps neighbouring strips (which
-  // share 8 halo columns) in one L2.
-  const int G = gridDim.x;
-  const int b = blockIdx.x;
-  const int L = (b % 8) * (G / 8) + b / 8;
-  if (L >= p.nblocks) return;  // whole block, before any barrier
-  const int strip = L % p.nstrips;
-  const int seg = L / p.nstrips;
-
   const int lane = threadIdx.x & (kLanes - 1);
   const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
   const int nx = p.nx, ny = p.ny;
-  const int x0 = strip * kStripOut;
-  const int x1 = min(x0 + kStripOut, nx);
-  const int y0 = seg * p.seg_rows;
-  const int y1 = min(y0 + p.seg_rows, ny);
-
-  for (int i = threadIdx.x; i < kRing * kQ * kLanes; i += kBlockThreads) ringP[i] = Real(0);
-  for (int i = threadIdx.x; i < kRing * (kQ - 1) * kLanes; i += kBlockThreads) ringR[i] = Real(0);
-
-  // This lane's column; loads and weights use the wrapped (periodic) or
-  // clamped (walled) column so every ring entry holds finite data.
-  const int c = x0 - kHalo + lane;
-  const int cm = p.per_x ? wrap(c, nx) : clampi(c, 0, nx - 1);
-  Real wxr[kWeightsPerNode];
-  {
-    const Real* wx = weights_x<Real>(p);
-#pragma unroll
-    for (int k = 0; k < kWeightsPerNode; ++k) wxr[k] = wx[cm * kWeightsPerNode + k];
-  }
-  const bool col_interior = p.per_x || (c >= 1 && c <= nx - 2);
-  const bool lane_r = lane >= 2 && lane < kLanes - 2;
-  const bool lane_o = lane >= kHalo && lane < kLanes - kHalo && c < x1;
-  const bool src_xl = !p.per_x && c == 1;
-  const bool src_xr = !p.per_x && c == nx - 2;
-
   const Store* __restrict__ src = static_cast<const Store*>(p.src);
   Store* __restrict__ dst = static_cast<Store*>(p.dst);
   const long long plane = p.plane;
 
-  Real qold[kQ], qnew[kQ];
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) qold[q] = qnew[q] = Real(0);
+  for (int i = threadIdx.x; i < kRing * kQ * kLanes; i += kBlockThreads) ringP[i] = Real(0);
+  for (int i = threadIdx.x; i < kRing * (kQ - 1) * kLanes; i += kBlockThreads) ringR[i] = Real(0);
 
-  const int niter = (y1 - y0 + kRowsPerIter - 1) / kRowsPerIter + 2;
+  // Work: the strips laid end to end form nstrips * ny strip-rows, cut into
+  // nblocks equal ranges (one per block, so every block does the same
+  // work).  A range may run over a strip boundary; each piece is marched
+  // separately.  XCD-aware order: the grid is a multiple of 8 and blocks are
+  // dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8; each XCD
+  // gets a contiguous run of ranges, which keeps a strip's consecutive
+  // segments and its neighbouring strips in one L2.
+  const int G = gridDim.x;
+  const int L = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
+  if (L >= p.nblocks) return;  // padding block: whole block, before any barrier
+  const long long total = static_cast<long long>(p.nstrips) * ny;
+  long long beg = total * L / p.nblocks;
+  const long long end = total * (L + 1) / p.nblocks;
 
-  // Row loads run two iterations ahead in two register buffers, so two
-  // iterations of loads are in flight while the stencil phases compute.
-  Store gA[kQ], gB[kQ];
-  auto load_row = [&](int pr, Store (&gb)[kQ]) {
-    const int prm = p.per_y ? wrap(pr, ny) : clampi(pr, 0, ny - 1);
-    const long long base = static_cast<long long>(prm) * p.pitch + cm;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) gb[q] = src[q * plane + base];
-  };
-  load_row(y0 - kHalo + t, gA);
-  load_row(y0 - kHalo + kRowsPerIter + t, gB);
-  __syncthreads();
+  while (beg < end) {  // uniform per block
+    const int strip = static_cast<int>(beg / ny);
+    const int y0 = static_cast<int>(beg % ny);
+    const int y1 = static_cast<int>(min(static_cast<long long>(ny), y0 + (end - beg)));
+    beg += y1 - y0;
 
-  auto iteration = [&](const int it, Store (&gb)[kQ]) {
-    const int p0 = y0 - kHalo + kRowsPerIter * it;
-
-    // ---- phase 1: P (to LDS) and Q (registers) of row p0 + t.
+    const int x0 = strip * kStripOut;
+    const int x1 = min(x0 + kStripOut, nx);
+    // This lane's column; loads and weights use the wrapped (periodic) or
+    // clamped (walled) column so every ring entry holds finite data.
+    const int c = x0 - kHalo + lane;
+    const int cm = p.per_x ? wrap(c, nx) : clampi(c, 0, nx - 1);
+    Real wxr[kWeightsPerNode];
     {
-      const int pr = p0 + t;
-      Real g[kQ];
+      const Real* wx = weights_x<Real>(p);
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) g[q] = Cvt<Store>::ld(gb[q]);
-      if (it + 2 < niter) load_row(pr + 2 * kRowsPerIter, gb);
-      double s, jx, jy;
-      moment_sums(g, s, jx, jy);
-      const double rho = 1.0 + s;
-      const double ir = recip(rho);
-      const double ux = jx * ir + p.half_dt * p.Fx;
-      const double uy = jy * ir + p.half_dt * p.Fy;
-      Real feq[kQ];
-      feq_dev(s, rho, ux, uy, feq);
-      Real F[kQ];
-      if (kForce) force_terms(p.Fx, p.Fy, ux, uy, feq, F);
-      const Real cPg = static_cast<Real>(p.cPg), cPe = static_cast<Real>(p.cPe);
-      const Real cQg = static_cast<Real>(p.cQg), cQe = static_cast<Real>(p.cQe);
-      Real* slotP = ringP + (pr & (kRing - 1)) * kQ * kLanes;
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        Real Pq = cPg * g[q] + cPe * feq[q];
-        Real Qq = cQg * g[q] + cQe * feq[q];
-        if (kForce) {
-          Pq += static_cast<Real>(p.cPF) * F[q];
-          Qq += static_cast<Real>(p.cQF) * F[q];
-        }
-        slotP[q * kLanes + lane] = Pq;
-        qnew[q] = Qq;
-      }
+      for (int k = 0; k < kWeightsPerNode; ++k) wxr[k] = wx[cm * kWeightsPerNode + k];
     }
-    __syncthreads();
+    const bool col_interior = p.per_x || (c >= 1 && c <= nx - 2);
+    const bool lane_r = lane >= 2 && lane < kLanes - 2;
+    const bool lane_o = lane >= kHalo && lane < kLanes - kHalo && c < x1;
+    const bool src_xl = !p.per_x && c == 1;
+    const bool src_xr = !p.per_x && c == nx - 2;
 
-    // ---- phase 2: S and R of row p0 - 2 + t (interior nodes), R to LDS.
-    {
-      const int r = p0 - 2 + t;
-      const bool row_ok =
-          r >= y0 - 2 && r < y1 + 2 && (p.per_y || (r >= 1 && r <= ny - 2));
-      if (row_ok && lane_r && col_interior) {
-        const int rm = p.per_y ? wrap(r, ny) : r;
-        const Real* wy = weights_y<Real>(p) + rm * kWeightsPerNode;
-        Real wyr[kWeightsPerNode];
+    Real qold[kQ], qnew[kQ];
 #pragma unroll
-        for (int k = 0; k < kWeightsPerNode; ++k) wyr[k] = wy[k];
-        // One base pointer per ring row (rows r-2 .. r+2) at this lane; every
-        // tap is then a compile-time offset (q plane, +-lane) of one of them.
-        // Only lanes 2..61 get here, so lane +- 2 stays inside the row.
-        const Real* rb[5];
+    for (int q = 0; q < kQ; ++q) qold[q] = qnew[q] = Real(0);
+
+    // Iterations come in pairs (one per prefetch buffer); a trailing extra
+    // iteration only reloads clamped rows and stores nothing (its rows fail
+    // the row checks below).
+    const int niter = ((y1 - y0 + kRowsPerIter - 1) / kRowsPerIter + 3) & ~1;
+
+    // Row loads run two iterations ahead in two register buffers, so two
+    // iterations of loads are in flight while the stencil phases compute.
+    Store gA[kQ], gB[kQ];
+    auto load_row = [&](int pr, Store (&gb)[kQ]) {
+      const int prm = p.per_y ? wrap(pr, ny) : clampi(pr, 0, ny - 1);
+      const long long base = static_cast<long long>(prm) * p.pitch + cm;
 #pragma unroll
-        for (int o = 0; o < 5; ++o) rb[o] = ringP + ((r + o - 2) & (kRing - 1)) * kQ * kLanes + lane;
-        const Real A = static_cast<Real>(p.A);
-        Real S[kQ];
+      for (int q = 0; q < kQ; ++q) gb[q] = src[q * plane + base];
+    };
+    load_row(y0 - kHalo + t, gA);
+    load_row(y0 - kHalo + kRowsPerIter + t, gB);
+    __syncthreads();  // ring zero-fill / previous piece complete
+
+    auto iteration = [&](const int it, Store (&gb)[kQ]) {
+      const int p0 = y0 - kHalo + kRowsPerIter * it;
+
+      // ---- phase 1: P (to LDS) and Q (registers) of row p0 + t.
+      {
+        const int pr = p0 + t;
+        Real g[kQ];
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-          const Real center = rb[2][q * kLanes];
-          Real acc = Real(0);
-          if (ex_of(q) != 0) {
-            const int sx = ex_of(q) > 0 ? 0 : 1;
-#pragma unroll
-            for (int k = 0; k < kTaps; ++k)
-              acc += wxr[sx * kTaps + k] * rb[2][q * kLanes + k + sx - 2];
-          }
-          if (ey_of(q) != 0) {
-            const int sy = ey_of(q) > 0 ? 0 : 1;
-#pragma unroll
-            for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][q * kLanes];
-          }
-          S[q] = center + A * acc;
-        }
-        const int slr = (r & (kRing - 1));
+        for (int q = 0; q < kQ; ++q) g[q] = Cvt<Store>::ld(gb[q]);
+        // Unconditional (rows are clamped or wrapped into the grid): the
+        // buffers then stay in fixed registers with their loads in flight.
+        load_row(pr + 2 * kRowsPerIter, gb);
         double s, jx, jy;
-        moment_sums(S, s, jx, jy);
+        moment_sums(g, s, jx, jy);
         const double rho = 1.0 + s;
         const double ir = recip(rho);
-        const double ux = jx * ir + p.half_h * p.Fx;
-        const double uy = jy * ir + p.half_h * p.Fy;
+        const double ux = jx * ir + p.half_dt * p.Fx;
+        const double uy = jy * ir + p.half_dt * p.Fy;
         Real feq[kQ];
         feq_dev(s, rho, ux, uy, feq);
         Real F[kQ];
         if (kForce) force_terms(p.Fx, p.Fy, ux, uy, feq, F);
-        const Real cRs = static_cast<Real>(p.cRs), cRe = static_cast<Real>(p.cRe);
-        Real R[kQ];
-        R[0] = Real(0);
-        Real* slotR = ringR + slr * (kQ - 1) * kLanes;
+        const Real cPg = static_cast<Real>(p.cPg), cPe = static_cast<Real>(p.cPe);
+        const Real cQg = static_cast<Real>(p.cQg), cQe = static_cast<Real>(p.cQe);
+        Real* slotP = ringP + (pr & (kRing - 1)) * kQ * kLanes;
 #pragma unroll
-        for (int q = 1; q < kQ; ++q) {
-          Real Rq = cRs * S[q] + cRe * feq[q];
-          if (kForce) Rq += static_cast<Real>(p.cRF) * F[q];
-          R[q] = Rq;
-          slotR[(q - 1) * kLanes + lane] = Rq;
+        for (int q = 0; q < kQ; ++q) {
+          Real Pq = cPg * g[q] + cPe * feq[q];
+          Real Qq = cQg * g[q] + cQe * feq[q];
+          if (kForce) {
+            Pq += static_cast<Real>(p.cPF) * F[q];
+            Qq += static_cast<Real>(p.cQF) * F[q];
+          }
+          slotP[q * kLanes + lane] = Pq;
+          qnew[q] = Qq;
         }
-        // Wall nodes whose nearest interior node is this one (eq 3.10 on
-        // f(t*); corners take the diagonal neighbour).  Physical f carries
-        // no force shift: u_f = sum xi R / rho = u*.
-        const bool src_yb = !p.per_y && r == 1;
-        const bool src_yt = !p.per_y && r == ny - 2;
-        if (kWalls && (src_xl || src_xr || src_yb || src_yt)) {
-          for (int dy = -1; dy <= 1; ++dy) {
-            if ((dy == -1 && !src_yb) || (dy == 1 && !src_yt)) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-              if ((dx == -1 && !src_xl) || (dx == 1 && !src_xr)) continue;
-              if (dx == 0 && dy == 0) continue;
-              double ub, vb;
-              wall_velocity(p, c + dx, r + dy, ub, vb);
-              Real sh[kQ];
-              nee_shift(rho, ux, uy, ub, vb, sh);
-              Real* slotW = ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
+      }
+      __syncthreads();
+
+      // ---- phase 2: S and R of row p0 - 2 + t (interior nodes), R to LDS.
+      // The whole wave computes (the x taps take neighbouring lanes' centre
+      // values); only interior lanes 2..61 store.
+      {
+        const int r = p0 - 2 + t;
+        const bool row_ok =
+            r >= y0 - 2 && r < y1 + 2 && (p.per_y || (r >= 1 && r <= ny - 2));
+        if (row_ok) {
+          const int rm = p.per_y ? wrap(r, ny) : r;
+          Real wyr[kWeightsPerNode];
+          row_weights(weights_y<Real>(p), rm, wyr);
+          // One base pointer per ring row r-2 .. r+2 at this lane.
+          const Real* rb[5];
 #pragma unroll
-              for (int q = 1; q < kQ; ++q) slotW[(q - 1) * kLanes + lane + dx] = R[q] + sh[q];
+          for (int o = 0; o < 5; ++o)
+            rb[o] = ringP + ((r + o - 2) & (kRing - 1)) * kQ * kLanes + lane;
+          const Real A = static_cast<Real>(p.A);
+          Real S[kQ];
+#pragma unroll
+          for (int q = 0; q < kQ; ++q) {
+            const Real centre = rb[2][q * kLanes];
+            Real acc = Real(0);
+            if (ex_of(q) > 0) acc = x_taps<0>(wxr, centre, acc);
+            if (ex_of(q) < 0) acc = x_taps<1>(wxr, centre, acc);
+            if (ey_of(q) != 0) {
+              const int sy = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+              for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][q * kLanes];
+            }
+            S[q] = centre + A * acc;
+          }
+          double s, jx, jy;
+          moment_sums(S, s, jx, jy);
+          const double rho = 1.0 + s;
+          const double ir = recip(rho);
+          const double ux = jx * ir + p.half_h * p.Fx;
+          const double uy = jy * ir + p.half_h * p.Fy;
+          Real feq[kQ];
+          feq_dev(s, rho, ux, uy, feq);
+          Real F[kQ];
+          if (kForce) force_terms(p.Fx, p.Fy, ux, uy, feq, F);
+          const Real cRs = static_cast<Real>(p.cRs), cRe = static_cast<Real>(p.cRe);
+          Real R[kQ];
+          R[0] = Real(0);
+#pragma unroll
+          for (int q = 1; q < kQ; ++q) {
+            Real Rq = cRs * S[q] + cRe * feq[q];
+            if (kForce) Rq += static_cast<Real>(p.cRF) * F[q];
+            R[q] = Rq;
+          }
+          if (lane_r && col_interior) {
+            Real* slotR = ringR + (r & (kRing - 1)) * (kQ - 1) * kLanes;
+#pragma unroll
+            for (int q = 1; q < kQ; ++q) slotR[(q - 1) * kLanes + lane] = R[q];
+            // Wall nodes whose nearest interior node is this one (eq 3.10
+            // on f(t*); corners take the diagonal neighbour).  Physical f
+            // carries no force shift: u_f = sum xi R / rho = u*.
+            const bool src_yb = !p.per_y && r == 1;
+            const bool src_yt = !p.per_y && r == ny - 2;
+            if (kWalls && (src_xl || src_xr || src_yb || src_yt)) {
+              for (int dy = -1; dy <= 1; ++dy) {
+                if ((dy == -1 && !src_yb) || (dy == 1 && !src_yt)) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                  if ((dx == -1 && !src_xl) || (dx == 1 && !src_xr)) continue;
+                  if (dx == 0 && dy == 0) continue;
+                  double ub, vb;
+                  wall_velocity(p, c + dx, r + dy, ub, vb);
+                  Real sh[kQ];
+                  nee_shift(rho, ux, uy, ub, vb, sh);
+                  Real* slotW = ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
+#pragma unroll
+                  for (int q = 1; q < kQ; ++q)
+                    slotW[(q - 1) * kLanes + lane + dx] = R[q] + sh[q];
+                }
+              }
             }
           }
         }
       }
-    }
-    __syncthreads();
+      __syncthreads();
 
-    // ---- phase 3: f~^{n+1} of row p0 - 4 + t.
-    {
-      const int o = p0 - 4 + t;
-      const bool row_ok = o >= y0 && o < y1 && (p.per_y || (o >= 1 && o <= ny - 2));
-      if (row_ok && lane_o && col_interior) {
-        const Real* wy = weights_y<Real>(p) + o * kWeightsPerNode;
-        Real wyr[kWeightsPerNode];
+      // ---- phase 3: f~^{n+1} of row p0 - 4 + t (whole wave computes,
+      // interior output lanes store).
+      {
+        const int o = p0 - 4 + t;
+        const bool row_ok = o >= y0 && o < y1 && (p.per_y || (o >= 1 && o <= ny - 2));
+        if (row_ok) {
+          Real wyr[kWeightsPerNode];
+          row_weights(weights_y<Real>(p), o, wyr);
+          const Real* rb[5];
 #pragma unroll
-        for (int k = 0; k < kWeightsPerNode; ++k) wyr[k] = wy[k];
-        // Lanes 4..59 only: lane +- 2 stays inside the row.
-        const Real* rb[5];
+          for (int k = 0; k < 5; ++k)
+            rb[k] = ringR + ((o + k - 2) & (kRing - 1)) * (kQ - 1) * kLanes + lane;
+          Real out[kQ];
+          out[0] = qold[0];
 #pragma unroll
-        for (int k = 0; k < 5; ++k)
-          rb[k] = ringR + ((o + k - 2) & (kRing - 1)) * (kQ - 1) * kLanes + lane;
-        Real out[kQ];
-        out[0] = qold[0];
+          for (int q = 1; q < kQ; ++q) {
+            const int pq = (q - 1) * kLanes;
+            const Real centre = rb[2][pq];
+            Real acc = qold[q];
+            if (ex_of(q) > 0) acc = x_taps<0>(wxr, centre, acc);
+            if (ex_of(q) < 0) acc = x_taps<1>(wxr, centre, acc);
+            if (ey_of(q) != 0) {
+              const int sy = ey_of(q) > 0 ? 0 : 1;
 #pragma unroll
-        for (int q = 1; q < kQ; ++q) {
-          const int pq = (q - 1) * kLanes;
-          Real acc = qold[q];
-          if (ex_of(q) != 0) {
-            const int sx = ex_of(q) > 0 ? 0 : 1;
-#pragma unroll
-            for (int k = 0; k < kTaps; ++k) acc += wxr[sx * kTaps + k] * rb[2][pq + k + sx - 2];
+              for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][pq];
+            }
+            out[q] = acc;
           }
-          if (ey_of(q) != 0) {
-            const int sy = ey_of(q) > 0 ? 0 : 1;
+          if (lane_o && col_interior) {
+            const long long base = static_cast<long long>(o) * p.pitch + c;
 #pragma unroll
-            for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][pq];
+            for (int q = 0; q < kQ; ++q) dst[q * plane + base] = Cvt<Store>::st(out[q]);
           }
-          out[q] = acc;
         }
-        const long long base = static_cast<long long>(o) * p.pitch + c;
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) dst[q * plane + base] = Cvt<Store>::st(out[q]);
-
       }
-    }
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) qold[q] = qnew[q];
-  };
+      for (int q = 0; q < kQ; ++q) qold[q] = qnew[q];
+    };
 
-  for (int it = 0; it < niter; it += 2) {
-    iteration(it, gA);
-    if (it + 1 < niter) iteration(it + 1, gB);
+    for (int it = 0; it < niter; it += 2) {
+      iteration(it, gA);
+      iteration(it + 1, gB);
+    }
+    __syncthreads();  // the next piece reuses the rings
   }
 }
 
@@ -680,6 +747,33 @@ size_t storage_bytes(int storage) {
     case kF16: { using Store = _Float16; CALL; } break;               \
     default: return hipErrorInvalidValue;                             \
   }
+
+template <typename Store>
+int occupancy_t(bool force, bool walls) {
+  int n = 0;
+  hipError_t e;
+  if (force)
+    e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<Store, true, true>,
+                                                             kBlockThreads, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<Store, true, false>,
+                                                             kBlockThreads, 0);
+  else
+    e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<Store, false, true>,
+                                                             kBlockThreads, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<Store, false, false>,
+                                                             kBlockThreads, 0);
+  return e == hipSuccess ? n : -1;
+}
+
+int step_blocks_per_cu(int storage, bool force, bool walls) {
+  switch (storage) {
+    case kF64: return occupancy_t<double>(force, walls);
+    case kF32: return occupancy_t<float>(force, walls);
+    case kBF16: return occupancy_t<Bf16>(force, walls);
+    case kF16: return occupancy_t<_Float16>(force, walls);
+    default: return -1;
+  }
+}
 
 hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s) {
   T2S2_DISPATCH(storage, return launch_step_t<Store>(p, grid, s));

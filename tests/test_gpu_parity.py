@@ -69,11 +69,12 @@ def test_cavity65_seeded_matches_oracle():
     _compare(case, g, d, u, v, ref)
 
 
-@pytest.mark.parametrize("segments", ["1", "3", "7"])
-def test_cavity_ragged_many_tiles(segments, monkeypatch):
-    """Non-square cavity spanning 3 strips (130 columns: 56 + 56 + 18) and
-    several row segments; ragged last strip and segment."""
-    monkeypatch.setenv("T2S2_SEGMENTS", segments)
+@pytest.mark.parametrize("blocks", ["8", "24", "64"])
+def test_cavity_ragged_many_tiles(blocks, monkeypatch):
+    """Non-square cavity spanning 3 strips (130 columns: 56 + 56 + 18) cut
+    into 8 to 64 block ranges, so ranges start mid-strip and run across strip
+    boundaries; ragged last strip."""
+    monkeypatch.setenv("T2S2_BLOCKS", blocks)
     case = W.cavity_case(64, lid=0.1, re=400.0, cfl=0.8, eta=0.1, noise=1e-6, seed=3)
     x = W.tanh_walled(129, 1.5)
     case.x = x
@@ -132,13 +133,13 @@ def test_rest_state_exact_zero():
 
 
 def test_tiling_invariance_bitwise(monkeypatch):
-    """Different row segmentations give bitwise-identical states (each output's
+    """Different work partitions give bitwise-identical states (each output's
     arithmetic is independent of the tiling; catches LDS ring races)."""
     case = W.cavity_case(96, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
     phi0 = oracle.init(case)
     outs = []
-    for segs in ("1", "5", "13"):
-        monkeypatch.setenv("T2S2_SEGMENTS", segs)
+    for blocks in ("8", "40", "96"):
+        monkeypatch.setenv("T2S2_BLOCKS", blocks)
         _, g, *_ = _gpu_run(case, phi0, 64)
         outs.append(g)
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
