@@ -135,6 +135,51 @@ int t2s2_read_distributions(t2s2_ctx* ctx, double* g);
  * out[3] > 0. */
 int t2s2_diagnostics(t2s2_ctx* ctx, double out[T2S2_NDIAG]);
 
+/* Relaxation parameter omega = dt / tau in use (0 without collision). */
+double t2s2_omega(const t2s2_ctx* ctx);
+
+/* ---- Discrete adjoint of the step (unforced flows) --------------------
+ * The reverse of the step above, stage by stage, for gradients of a loss of
+ * the state with respect to the initial fields and the viscosity.  Adjoint
+ * states lambda (dL/dg for g = f~ - w) live in device buffers of
+ * t2s2_adjoint_state_bytes() bytes: FP64 for T2S2_F64 storage, FP32
+ * otherwise, in the state's pitched [9][ny][pitch] layout. */
+
+/* Bytes of one adjoint state buffer. */
+size_t t2s2_adjoint_state_bytes(const t2s2_ctx* ctx);
+
+/* Bytes of the adjoint scratch (recomputed intermediates, partial sums). */
+size_t t2s2_adjoint_scratch_bytes(const t2s2_ctx* ctx);
+
+/* Attach the adjoint scratch (device, 256-byte aligned).  Returns
+ * T2S2_ERR_UNSUPPORTED for forced flows.  No device call. */
+int t2s2_bind_adjoint(t2s2_ctx* ctx, void* scratch);
+
+/* lambda = d(<gu, u> + <gv, v>)/dg of the velocity of eq 3.3 at every node,
+ * for a state buffer `state` of this context (storage layout).  gu, gv:
+ * device FP64 [ny][nx] (either may be NULL).  Asynchronous. */
+int t2s2_adjoint_seed_velocity(t2s2_ctx* ctx, const void* state, const double* gu,
+                               const double* gv, void* lam);
+
+/* lam_n = (d f~^{n+1} / d f~^n)^T lam_np1 for the step taken from the
+ * state `state_n` (storage layout).  If domega_accum (device, one double) is
+ * non-NULL, adds <lam_np1, d f~^{n+1}/d omega> to it; dL/dnu = dL/domega *
+ * (-omega / nu).  lam_np1 and lam_n must differ.  Asynchronous;
+ * deterministic (fixed reduction order). */
+int t2s2_adjoint_step(t2s2_ctx* ctx, const void* state_n, const void* lam_np1, void* lam_n,
+                      double* domega_accum);
+
+/* Gradients of the equilibrium initial state f~ = f^eq(rho, u) (Sec. 3):
+ * grho = dL/drho, gux = dL/dux, guy = dL/duy from lam0 = dL/dg^0.  Device
+ * FP64 [ny][nx] fields; outputs may be NULL.  Asynchronous. */
+int t2s2_adjoint_init_macro(t2s2_ctx* ctx, const void* lam0, const double* rho,
+                            const double* ux, const double* uy, double* grho, double* gux,
+                            double* guy);
+
+/* Copy an adjoint state to / from dense FP64 [9][ny][nx] device memory. */
+int t2s2_adjoint_read(t2s2_ctx* ctx, const void* lam, double* out);
+int t2s2_adjoint_load(t2s2_ctx* ctx, const double* in, void* lam);
+
 void t2s2_destroy(t2s2_ctx* ctx);
 
 /* Message of the last failing call on this thread ("" if none). */

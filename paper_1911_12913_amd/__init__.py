@@ -82,6 +82,15 @@ def load_library(path: str = LIB_PATH):
         "t2s2_moments": (i, [vp, vp, vp, vp]),
         "t2s2_read_distributions": (i, [vp, vp]),
         "t2s2_diagnostics": (i, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "t2s2_omega": (d, [vp]),
+        "t2s2_adjoint_state_bytes": (sz, [vp]),
+        "t2s2_adjoint_scratch_bytes": (sz, [vp]),
+        "t2s2_bind_adjoint": (i, [vp, vp]),
+        "t2s2_adjoint_seed_velocity": (i, [vp, vp, vp, vp, vp]),
+        "t2s2_adjoint_step": (i, [vp, vp, vp, vp, vp]),
+        "t2s2_adjoint_init_macro": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
+        "t2s2_adjoint_read": (i, [vp, vp, vp]),
+        "t2s2_adjoint_load": (i, [vp, vp, vp]),
         "t2s2_destroy": (None, [vp]),
         "t2s2_last_error": (ctypes.c_char_p, []),
     }
@@ -97,7 +106,10 @@ def exported_symbols() -> Sequence[str]:
     return ("t2s2_create", "t2s2_state_bytes", "t2s2_workspace_bytes", "t2s2_bind",
             "t2s2_init_macro", "t2s2_init_distributions", "t2s2_step", "t2s2_current",
             "t2s2_steps_taken", "t2s2_dt", "t2s2_moments", "t2s2_read_distributions",
-            "t2s2_diagnostics", "t2s2_destroy", "t2s2_last_error")
+            "t2s2_diagnostics", "t2s2_omega", "t2s2_adjoint_state_bytes",
+            "t2s2_adjoint_scratch_bytes", "t2s2_bind_adjoint", "t2s2_adjoint_seed_velocity",
+            "t2s2_adjoint_step", "t2s2_adjoint_init_macro", "t2s2_adjoint_read",
+            "t2s2_adjoint_load", "t2s2_destroy", "t2s2_last_error")
 
 
 def _check(rc: int):
@@ -221,6 +233,72 @@ class Context:
         g = t.empty((9, self.ny, self.nx), dtype=t.float64, device=self.device)
         _check(_lib.t2s2_read_distributions(self._h, g.data_ptr()))
         return g
+
+    @property
+    def omega(self) -> float:
+        return float(_lib.t2s2_omega(self._h))
+
+    # -- raw state buffers (checkpoint / restore)
+    def state_tensor(self):
+        """The bound buffer holding the current state (raw storage bytes)."""
+        return self.state[self.current]
+
+    def save_state(self):
+        return self.state_tensor().clone()
+
+    def restore_state(self, saved, steps_taken: Optional[int] = None):
+        self.state_tensor().copy_(saved)
+
+    # -- adjoint
+    def enable_adjoint(self):
+        """Allocate and bind the adjoint scratch (idempotent)."""
+        if getattr(self, "adjoint_scratch", None) is None:
+            t = self._torch
+            n = int(_lib.t2s2_adjoint_scratch_bytes(self._h))
+            self.adjoint_scratch = t.empty(n, dtype=t.uint8, device=self.device)
+            _check(_lib.t2s2_bind_adjoint(self._h, self.adjoint_scratch.data_ptr()))
+
+    def adjoint_buffer(self):
+        t = self._torch
+        return t.empty(int(_lib.t2s2_adjoint_state_bytes(self._h)), dtype=t.uint8,
+                       device=self.device)
+
+    def adjoint_seed_velocity(self, state, gu, gv, lam):
+        shp = (self.ny, self.nx)
+        gu = self._f64(gu, shp) if gu is not None else None
+        gv = self._f64(gv, shp) if gv is not None else None
+        self._keep_adj = (gu, gv)
+        _check(_lib.t2s2_adjoint_seed_velocity(
+            self._h, state.data_ptr(), gu.data_ptr() if gu is not None else None,
+            gv.data_ptr() if gv is not None else None, lam.data_ptr()))
+
+    def adjoint_step(self, state, lam_np1, lam_n, domega=None):
+        _check(_lib.t2s2_adjoint_step(self._h, state.data_ptr(), lam_np1.data_ptr(),
+                                      lam_n.data_ptr(),
+                                      domega.data_ptr() if domega is not None else None))
+
+    def adjoint_init_macro(self, lam0, rho, ux, uy):
+        t = self._torch
+        shp = (self.ny, self.nx)
+        r, u, v = self._f64(rho, shp), self._f64(ux, shp), self._f64(uy, shp)
+        out = [t.empty(shp, dtype=t.float64, device=self.device) for _ in range(3)]
+        _check(_lib.t2s2_adjoint_init_macro(self._h, lam0.data_ptr(), r.data_ptr(),
+                                            u.data_ptr(), v.data_ptr(),
+                                            *[o.data_ptr() for o in out]))
+        return tuple(out)
+
+    def adjoint_read(self, lam):
+        t = self._torch
+        out = t.empty((9, self.ny, self.nx), dtype=t.float64, device=self.device)
+        _check(_lib.t2s2_adjoint_read(self._h, lam.data_ptr(), out.data_ptr()))
+        return out
+
+    def adjoint_load(self, dense):
+        d = self._f64(dense, (9, self.ny, self.nx))
+        lam = self.adjoint_buffer()
+        _check(_lib.t2s2_adjoint_load(self._h, d.data_ptr(), lam.data_ptr()))
+        self._keep_adj = (d,)
+        return lam
 
     def diagnostics(self, raise_nonfinite: bool = True) -> dict:
         out = (ctypes.c_double * NDIAG)()

@@ -1,0 +1,599 @@
+// Discrete adjoint of the fused T2S2-FDLBM step (unforced flows).
+//
+// The forward step, stage by stage (g = f~^n - w, all populations as
+// deviations from the rest state):
+//   [1] P = cPg g + cPe (feq(g) - w),  Q = cQg g + cQe (feq(g) - w)   all nodes
+//   [2] S = P + A L(P)                                          interior nodes
+//   [3] R = cRs S + cRe (feq(S) - w)                            interior nodes
+//   [4] R_b = R_f + feq(rho_f, u_b) - feq(rho_f, u_f), moments of S_f   walls
+//   [5] o = Q + L(R)                                            interior nodes
+//   [6] o_b = o_f + feq(rho_f, u_b) - feq(rho_f, u_f), moments of o_f   walls
+// with L the dt-scaled mixed-difference operator -dt xi . grad.  The
+// adjoint runs [6]..[1] in reverse with the transposed stencil (a gather
+// over the nodes whose stencil reads this one, with their weights) and the
+// transposed moment Jacobians of the equilibrium.  Every kernel is
+// node-parallel over materialised intermediates; the wall-to-fluid scatter
+// of [4] and [6] is gathered at the fluid node, so no atomics are needed and
+// the result is deterministic.  d/d omega of the step (omega = dt / tau)
+// enters only through the pointwise coefficients; its inner products with
+// the adjoints are reduced in a fixed block order.
+#include <hip/hip_runtime.h>
+
+#include "t2s2_device.h"
+#include "t2s2_internal.h"
+
+namespace t2s2 {
+namespace {
+
+template <typename Real>
+__device__ inline const Real* wtab_x(const AdjParams& a);
+template <>
+__device__ inline const double* wtab_x<double>(const AdjParams& a) {
+  return a.wx;
+}
+template <>
+__device__ inline const float* wtab_x<float>(const AdjParams& a) {
+  return a.wx32;
+}
+template <typename Real>
+__device__ inline const Real* wtab_y(const AdjParams& a);
+template <>
+__device__ inline const double* wtab_y<double>(const AdjParams& a) {
+  return a.wy;
+}
+template <>
+__device__ inline const float* wtab_y<float>(const AdjParams& a) {
+  return a.wy32;
+}
+
+__device__ inline bool interior(const AdjParams& a, int x, int y) {
+  return (a.per_x || (x >= 1 && x <= a.nx - 2)) && (a.per_y || (y >= 1 && y <= a.ny - 2));
+}
+
+// Neighbour along an axis; -1 when it falls outside a walled axis.
+__device__ inline int along(int i, int off, int n, int per) {
+  const int j = i + off;
+  if (per) return j < 0 ? j + n : (j >= n ? j - n : j);
+  return (j < 0 || j >= n) ? -1 : j;
+}
+
+// Offset of tap k for velocity sign class s (0: positive, 1: negative).
+__device__ inline int tap_offset(int s, int k) { return s == 0 ? k - 2 : k - 1; }
+
+// X_q(u) = 3 e + 9/2 e^2 - 3/2 |u|^2 and dX_q/du = (3 + 9 e) xi_q - 3 u.
+__device__ inline double Xq(int q, double ux, double uy) {
+  const double e = ex_of(q) * ux + ey_of(q) * uy;
+  return e * (3.0 + 4.5 * e) - 1.5 * (ux * ux + uy * uy);
+}
+
+// Moments rho, u of a node (unforced: u = sum xi g / rho).
+template <typename T>
+__device__ inline void node_rho_u(const T v[kQ], double& rho, double& ux, double& uy) {
+  double s, jx, jy;
+  moment_sums(v, s, jx, jy);
+  rho = 1.0 + s;
+  ux = jx / rho;
+  uy = jy / rho;
+}
+
+// Transpose of d(sum_q mu_q F_q)/dg for a pointwise map whose dependence on
+// g goes only through (rho, u): given a = dF/drho . mu and b = dF/du . mu,
+// the gradient is a + b . (xi_q - u) / rho.
+template <typename Real>
+__device__ inline void through_moments(double rho, double ux, double uy, double a, double bx,
+                                       double by, Real out[kQ], bool accumulate) {
+  const double ir = 1.0 / rho;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const double g = a + (bx * (ex_of(q) - ux) + by * (ey_of(q) - uy)) * ir;
+    out[q] = accumulate ? out[q] + static_cast<Real>(g) : static_cast<Real>(g);
+  }
+}
+
+// (a, b) for F = feq(rho, u) - w:  dF_q = w_q [(1 + X_q) drho + rho dX_q].
+template <typename Real>
+__device__ inline void feq_ab(double rho, double ux, double uy, const Real mu[kQ], double& a,
+                              double& bx, double& by) {
+  a = 0.0;
+  bx = 0.0;
+  by = 0.0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const double m = static_cast<double>(mu[q]) * w_of(q);
+    const double e = ex_of(q) * ux + ey_of(q) * uy;
+    a += m * (1.0 + Xq(q, ux, uy));
+    bx += m * ((3.0 + 9.0 * e) * ex_of(q) - 3.0 * ux);
+    by += m * ((3.0 + 9.0 * e) * ey_of(q) - 3.0 * uy);
+  }
+  bx *= rho;
+  by *= rho;
+}
+
+// (a, b) for the extrapolation shift F = feq(rho, u_b) - feq(rho, u):
+//   dF_q = w_q [(X_q(u_b) - X_q(u)) drho - rho dX_q(u)].
+template <typename Real>
+__device__ inline void shift_ab(double rho, double ux, double uy, double ub, double vb,
+                                const Real mu[kQ], double& a, double& bx, double& by) {
+  a = 0.0;
+  bx = 0.0;
+  by = 0.0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const double m = static_cast<double>(mu[q]) * w_of(q);
+    const double e = ex_of(q) * ux + ey_of(q) * uy;
+    a += m * (Xq(q, ub, vb) - Xq(q, ux, uy));
+    bx -= m * ((3.0 + 9.0 * e) * ex_of(q) - 3.0 * ux);
+    by -= m * ((3.0 + 9.0 * e) * ey_of(q) - 3.0 * uy);
+  }
+  bx *= rho;
+  by *= rho;
+}
+
+__device__ inline void wall_vel(const AdjParams& a, int c, int r, double& ub, double& vb) {
+  int side;
+  if (!a.per_x && c == 0)
+    side = 0;
+  else if (!a.per_x && c == a.nx - 1)
+    side = 1;
+  else if (!a.per_y && r == 0)
+    side = 2;
+  else
+    side = 3;
+  ub = a.uw[side][0];
+  vb = a.uw[side][1];
+}
+
+// Calls fn(bx, by) for every wall node whose nearest interior node is
+// (x, y) (the node itself must be interior).
+template <typename Fn>
+__device__ inline void for_wall_dependents(const AdjParams& a, int x, int y, Fn fn) {
+  const bool xl = !a.per_x && x == 1, xr = !a.per_x && x == a.nx - 2;
+  const bool yb = !a.per_y && y == 1, yt = !a.per_y && y == a.ny - 2;
+  if (!(xl || xr || yb || yt)) return;
+  for (int dy = -1; dy <= 1; ++dy) {
+    if ((dy == -1 && !yb) || (dy == 1 && !yt)) continue;
+    for (int dx = -1; dx <= 1; ++dx) {
+      if ((dx == -1 && !xl) || (dx == 1 && !xr)) continue;
+      if (dx == 0 && dy == 0) continue;
+      fn(x + dx, y + dy);
+    }
+  }
+}
+
+#define NODE_LOOP(a)                                                                      \
+  for (long long node = blockIdx.x * 256LL + threadIdx.x,                                 \
+                 nn = static_cast<long long>((a).nx) * (a).ny;                            \
+       node < nn; node += 256LL * gridDim.x)
+
+template <typename T>
+__device__ inline void load9(const T* base, long long plane, long long off, T v[kQ]) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) v[q] = base[q * plane + off];
+}
+
+// ---- [1] forward recompute: P at all nodes.
+template <typename Store>
+__global__ __launch_bounds__(256) void adj_fwd_P(AdjParams a, const Store* g) {
+  using Real = typename Cvt<Store>::R;
+  Real* P = static_cast<Real*>(a.P);
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    Real v[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * a.plane + off]);
+    double rho, ux, uy;
+    node_rho_u(v, rho, ux, uy);
+    Real feq[kQ];
+    feq_dev(rho - 1.0, rho, ux, uy, feq);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+      P[q * a.plane + off] =
+          static_cast<Real>(a.cPg) * v[q] + static_cast<Real>(a.cPe) * feq[q];
+  }
+}
+
+// ---- [2] forward recompute: S = P + A L(P) at interior nodes.
+template <typename Real>
+__global__ __launch_bounds__(256) void adj_fwd_S(AdjParams a) {
+  const Real* P = static_cast<const Real*>(a.P);
+  Real* S = static_cast<Real*>(a.S);
+  const Real* WX = wtab_x<Real>(a);
+  const Real* WY = wtab_y<Real>(a);
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    if (!interior(a, x, y)) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) S[q * a.plane + off] = Real(0);
+      continue;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      Real acc = Real(0);
+      if (ex_of(q) != 0) {
+        const int s = ex_of(q) > 0 ? 0 : 1;
+        for (int k = 0; k < kTaps; ++k) {
+          const int xx = along(x, tap_offset(s, k), a.nx, a.per_x);
+          const Real w = WX[x * kWeightsPerNode + s * kTaps + k];
+          if (xx >= 0) acc += w * P[q * a.plane + static_cast<long long>(y) * a.pitch + xx];
+        }
+      }
+      if (ey_of(q) != 0) {
+        const int s = ey_of(q) > 0 ? 0 : 1;
+        for (int k = 0; k < kTaps; ++k) {
+          const int yy = along(y, tap_offset(s, k), a.ny, a.per_y);
+          const Real w = WY[y * kWeightsPerNode + s * kTaps + k];
+          if (yy >= 0) acc += w * P[q * a.plane + static_cast<long long>(yy) * a.pitch + x];
+        }
+      }
+      S[q * a.plane + off] = P[q * a.plane + off] + static_cast<Real>(a.A) * acc;
+    }
+  }
+}
+
+// ---- [6'] mu = adjoint of the interior output including the wall rows
+// extrapolated from it; zero on walls.
+template <typename Store>
+__global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* next,
+                                                      const typename Cvt<Store>::R* lam) {
+  using Real = typename Cvt<Store>::R;
+  Real* mu = static_cast<Real*>(a.mu);
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    Real m[kQ];
+    if (!interior(a, x, y)) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) mu[q * a.plane + off] = Real(0);
+      continue;
+    }
+    load9(lam, a.plane, off, m);
+    bool first = true;
+    double rho = 1, ux = 0, uy = 0;
+    for_wall_dependents(a, x, y, [&](int bx, int by) {
+      if (first) {
+        Real o[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) o[q] = Cvt<Store>::ld(next[q * a.plane + off]);
+        node_rho_u(o, rho, ux, uy);
+        first = false;
+      }
+      const long long boff = static_cast<long long>(by) * a.pitch + bx;
+      Real lb[kQ];
+      load9(lam, a.plane, boff, lb);
+      double ub, vb;
+      wall_vel(a, bx, by, ub, vb);
+      double sa, sbx, sby;
+      shift_ab(rho, ux, uy, ub, vb, lb, sa, sbx, sby);
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) m[q] += lb[q];
+      through_moments(rho, ux, uy, sa, sbx, sby, m, true);
+    });
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) mu[q * a.plane + off] = m[q];
+  }
+}
+
+// Transposed stencil: out[m] = sum over interior nodes i whose stencil
+// reads m of w_k(i) in[i] (populations 1..8).
+template <typename Real>
+__device__ inline Real stencil_T(const AdjParams& a, const Real* in, const Real* WX,
+                                 const Real* WY, int q, int x, int y) {
+  Real acc = Real(0);
+  if (ex_of(q) != 0) {
+    const int s = ex_of(q) > 0 ? 0 : 1;
+    for (int k = 0; k < kTaps; ++k) {
+      const int xi = along(x, -tap_offset(s, k), a.nx, a.per_x);
+      if (xi >= 0 && interior(a, xi, y))
+        acc += WX[xi * kWeightsPerNode + s * kTaps + k] *
+               in[q * a.plane + static_cast<long long>(y) * a.pitch + xi];
+    }
+  }
+  if (ey_of(q) != 0) {
+    const int s = ey_of(q) > 0 ? 0 : 1;
+    for (int k = 0; k < kTaps; ++k) {
+      const int yi = along(y, -tap_offset(s, k), a.ny, a.per_y);
+      if (yi >= 0 && interior(a, x, yi))
+        acc += WY[yi * kWeightsPerNode + s * kTaps + k] *
+               in[q * a.plane + static_cast<long long>(yi) * a.pitch + x];
+    }
+  }
+  return acc;
+}
+
+// ---- [5'] lamR = L^T mu at every node (population 0: no stencil).
+template <typename Real>
+__global__ __launch_bounds__(256) void adj_R(AdjParams a) {
+  const Real* mu = static_cast<const Real*>(a.mu);
+  Real* lamR = static_cast<Real*>(a.lamR);
+  const Real* WX = wtab_x<Real>(a);
+  const Real* WY = wtab_y<Real>(a);
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    lamR[off] = Real(0);
+#pragma unroll
+    for (int q = 1; q < kQ; ++q) lamR[q * a.plane + off] = stencil_T(a, mu, WX, WY, q, x, y);
+  }
+}
+
+// ---- [4'] + [3'] lamS at interior nodes (zero on walls), with the
+// d/d omega inner product of the R stage.
+template <typename Real>
+__global__ __launch_bounds__(256) void adj_S(AdjParams a, double* partial) {
+  __shared__ double red[256];
+  const Real* S = static_cast<const Real*>(a.S);
+  const Real* lamR = static_cast<const Real*>(a.lamR);
+  Real* lamS = static_cast<Real*>(a.lamS);
+  double dw = 0.0;
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    if (!interior(a, x, y)) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) lamS[q * a.plane + off] = Real(0);
+      continue;
+    }
+    Real s[kQ], lr[kQ];
+    load9(S, a.plane, off, s);
+    load9(lamR, a.plane, off, lr);
+    double rho, ux, uy;
+    node_rho_u(s, rho, ux, uy);
+    Real ls[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) ls[q] = Real(0);
+    for_wall_dependents(a, x, y, [&](int bx, int by) {
+      const long long boff = static_cast<long long>(by) * a.pitch + bx;
+      Real lb[kQ];
+      load9(lamR, a.plane, boff, lb);
+      double ub, vb;
+      wall_vel(a, bx, by, ub, vb);
+      double sa, sbx, sby;
+      shift_ab(rho, ux, uy, ub, vb, lb, sa, sbx, sby);
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) lr[q] += lb[q];
+      through_moments(rho, ux, uy, sa, sbx, sby, ls, true);
+    });
+    Real feq[kQ];
+    feq_dev(rho - 1.0, rho, ux, uy, feq);
+    double fa, fbx, fby;
+    feq_ab(rho, ux, uy, lr, fa, fbx, fby);
+    const double cRe = a.cRe;
+    Real jt[kQ];
+    through_moments(rho, ux, uy, cRe * fa, cRe * fbx, cRe * fby, jt, false);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      lamS[q * a.plane + off] = ls[q] + static_cast<Real>(a.cRs) * lr[q] + jt[q];
+      dw += static_cast<double>(lr[q]) * a.dcRs * static_cast<double>(s[q] - feq[q]);
+    }
+  }
+  red[threadIdx.x] = dw;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ---- [2'] lamP = [interior] lamS + A L^T lamS at every node.  Written
+// into the P buffer (P is not needed after [2]).
+template <typename Real>
+__global__ __launch_bounds__(256) void adj_P(AdjParams a) {
+  const Real* lamS = static_cast<const Real*>(a.lamS);
+  Real* lamP = static_cast<Real*>(a.P);
+  const Real* WX = wtab_x<Real>(a);
+  const Real* WY = wtab_y<Real>(a);
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    const bool in = interior(a, x, y);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      Real v = in ? lamS[q * a.plane + off] : Real(0);
+      if (q != 0) v += static_cast<Real>(a.A) * stencil_T(a, lamS, WX, WY, q, x, y);
+      lamP[q * a.plane + off] = v;
+    }
+  }
+}
+
+// ---- [1'] lam_n from lamP and lamQ (= mu), with the d/d omega inner
+// products of the P and Q stages.
+template <typename Store>
+__global__ __launch_bounds__(256) void adj_g(AdjParams a, const Store* g,
+                                              typename Cvt<Store>::R* lam_out, double* partial) {
+  using Real = typename Cvt<Store>::R;
+  __shared__ double red[256];
+  const Real* lamP = static_cast<const Real*>(a.P);
+  const Real* lamQ = static_cast<const Real*>(a.mu);
+  double dw = 0.0;
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    Real v[kQ], lp[kQ], lq[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * a.plane + off]);
+    load9(lamP, a.plane, off, lp);
+    load9(lamQ, a.plane, off, lq);
+    double rho, ux, uy;
+    node_rho_u(v, rho, ux, uy);
+    Real feq[kQ], mix[kQ];
+    feq_dev(rho - 1.0, rho, ux, uy, feq);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+      mix[q] = static_cast<Real>(a.cPe) * lp[q] + static_cast<Real>(a.cQe) * lq[q];
+    double fa, fbx, fby;
+    feq_ab(rho, ux, uy, mix, fa, fbx, fby);
+    Real out[kQ];
+    through_moments(rho, ux, uy, fa, fbx, fby, out, false);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      out[q] += static_cast<Real>(a.cPg) * lp[q] + static_cast<Real>(a.cQg) * lq[q];
+      lam_out[q * a.plane + off] = out[q];
+      dw += (a.dcPg * static_cast<double>(lp[q]) + a.dcQg * static_cast<double>(lq[q])) *
+            static_cast<double>(v[q] - feq[q]);
+    }
+  }
+  red[threadIdx.x] = dw;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(64) void adj_accumulate(const double* partial, int n,
+                                                      double* accum) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < n; ++b) s += partial[b];
+    *accum += s;
+  }
+}
+
+// ---- seed: lam = d(<gu, u> + <gv, v>)/dg at every node.
+template <typename Store>
+__global__ __launch_bounds__(256) void adj_seed_velocity(AdjParams a, const Store* g,
+                                                          const double* gu, const double* gv,
+                                                          typename Cvt<Store>::R* lam) {
+  using Real = typename Cvt<Store>::R;
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    Real v[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * a.plane + off]);
+    double rho, ux, uy;
+    node_rho_u(v, rho, ux, uy);
+    Real out[kQ];
+    through_moments(rho, ux, uy, 0.0, gu ? gu[node] : 0.0, gv ? gv[node] : 0.0, out, false);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) lam[q * a.plane + off] = out[q];
+  }
+}
+
+// ---- gradient of the equilibrium initial state f~ = feq(rho, u).
+template <typename Real>
+__global__ __launch_bounds__(256) void adj_init_macro(AdjParams a, const Real* lam,
+                                                       const double* rho, const double* ux,
+                                                       const double* uy, double* grho,
+                                                       double* gux, double* guy) {
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    Real l[kQ];
+    load9(lam, a.plane, off, l);
+    double fa, fbx, fby;
+    feq_ab(rho[node], ux[node], uy[node], l, fa, fbx, fby);
+    if (grho) grho[node] = fa;
+    if (gux) gux[node] = fbx;
+    if (guy) guy[node] = fby;
+  }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void adj_convert(AdjParams a, const Real* lam, double* dense,
+                                                    const double* dense_in, Real* lam_out) {
+  NODE_LOOP(a) {
+    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+    const long long off = static_cast<long long>(y) * a.pitch + x;
+    const long long n = static_cast<long long>(a.nx) * a.ny;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      if (dense) dense[q * n + node] = static_cast<double>(lam[q * a.plane + off]);
+      if (lam_out) lam_out[q * a.plane + off] = static_cast<Real>(dense_in[q * n + node]);
+    }
+  }
+}
+
+int adj_grid(const AdjParams& a) {
+  long long g = (static_cast<long long>(a.nx) * a.ny + 255) / 256;
+  return static_cast<int>(g < 1 ? 1 : (g > kDiagBlocks ? kDiagBlocks : g));
+}
+
+template <typename Store>
+hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp, int step_grid,
+                          const void* state_n, const void* lam_np1, void* lam_n,
+                          double* partial, double* accum, hipStream_t s) {
+  using Real = typename Cvt<Store>::R;
+  const int G = kDiagBlocks;  // fixed grid: the reductions are deterministic
+  // f~^{n+1} again, into the scratch state (the walls' adjoint needs its
+  // moments at the fluid nodes).
+  StepParams fwd = sp;
+  fwd.src = state_n;
+  fwd.dst = a.next;
+  hipError_t e = launch_step(storage, fwd, step_grid, s);
+  if (e != hipSuccess) return e;
+  const Store* g = static_cast<const Store*>(state_n);
+  hipLaunchKernelGGL(adj_fwd_P<Store>, dim3(G), dim3(256), 0, s, a, g);
+  hipLaunchKernelGGL(adj_fwd_S<Real>, dim3(G), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(adj_out_walls<Store>, dim3(G), dim3(256), 0, s, a,
+                     static_cast<const Store*>(a.next), static_cast<const Real*>(lam_np1));
+  hipLaunchKernelGGL(adj_R<Real>, dim3(G), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(adj_S<Real>, dim3(G), dim3(256), 0, s, a, partial);
+  hipLaunchKernelGGL(adj_P<Real>, dim3(G), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(adj_g<Store>, dim3(G), dim3(256), 0, s, a, g, static_cast<Real*>(lam_n),
+                     partial + G);
+  if (accum) hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, 2 * G, accum);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define T2S2_ADJ_DISPATCH(storage, CALL)                   \
+  switch (storage) {                                       \
+    case kF64: { using Store = double; CALL; } break;      \
+    case kF32: { using Store = float; CALL; } break;       \
+    case kBF16: { using Store = Bf16; CALL; } break;       \
+    case kF16: { using Store = _Float16; CALL; } break;    \
+    default: return hipErrorInvalidValue;                  \
+  }
+
+size_t adjoint_real_bytes(int storage) { return storage == kF64 ? 8 : 4; }
+
+hipError_t launch_adjoint_step(int storage, const AdjParams& a, const StepParams& sp,
+                               int step_grid, const void* state_n, const void* lam_np1,
+                               void* lam_n, double* partial, double* accum, hipStream_t s) {
+  T2S2_ADJ_DISPATCH(storage, return adjoint_step_t<Store>(storage, a, sp, step_grid, state_n,
+                                                          lam_np1, lam_n, partial, accum, s));
+  return hipSuccess;
+}
+
+hipError_t launch_adjoint_seed(int storage, const AdjParams& a, const void* state,
+                               const double* gu, const double* gv, void* lam, hipStream_t s) {
+  T2S2_ADJ_DISPATCH(storage,
+                    hipLaunchKernelGGL(adj_seed_velocity<Store>, dim3(adj_grid(a)), dim3(256), 0,
+                                       s, a, static_cast<const Store*>(state), gu, gv,
+                                       static_cast<typename Cvt<Store>::R*>(lam)));
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init(int storage, const AdjParams& a, const void* lam,
+                               const double* rho, const double* ux, const double* uy,
+                               double* grho, double* gux, double* guy, hipStream_t s) {
+  if (storage == kF64)
+    hipLaunchKernelGGL(adj_init_macro<double>, dim3(adj_grid(a)), dim3(256), 0, s, a,
+                       static_cast<const double*>(lam), rho, ux, uy, grho, gux, guy);
+  else
+    hipLaunchKernelGGL(adj_init_macro<float>, dim3(adj_grid(a)), dim3(256), 0, s, a,
+                       static_cast<const float*>(lam), rho, ux, uy, grho, gux, guy);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_convert(int storage, const AdjParams& a, const void* lam,
+                                  double* dense, const double* dense_in, void* lam_out,
+                                  hipStream_t s) {
+  if (storage == kF64)
+    hipLaunchKernelGGL(adj_convert<double>, dim3(adj_grid(a)), dim3(256), 0, s, a,
+                       static_cast<const double*>(lam), dense, dense_in,
+                       static_cast<double*>(lam_out));
+  else
+    hipLaunchKernelGGL(adj_convert<float>, dim3(adj_grid(a)), dim3(256), 0, s, a,
+                       static_cast<const float*>(lam), dense, dense_in,
+                       static_cast<float*>(lam_out));
+  return hipGetLastError();
+}
+
+}  // namespace t2s2

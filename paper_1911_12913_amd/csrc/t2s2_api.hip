@@ -137,6 +137,11 @@ struct t2s2_ctx {
   StepParams sp{};
   AuxParams ap{};
   int grid = 0;
+  // adjoint
+  AdjParams adj{};
+  bool adj_bound = false;
+  double* adj_partial = nullptr;
+  size_t adj_state_bytes = 0;
 };
 
 extern "C" {
@@ -416,6 +421,126 @@ int t2s2_diagnostics(t2s2_ctx* c, double out[T2S2_NDIAG]) {
   if (e != hipSuccess) return hip_fail(e, "diagnostics: synchronize");
   for (int k = 0; k < T2S2_NDIAG; ++k) out[k] = host[k];
   if (host[3] > 0.0) return fail(T2S2_ERR_NONFINITE, "non-finite populations in the state");
+  return T2S2_OK;
+}
+
+double t2s2_omega(const t2s2_ctx* c) { return c ? c->omega : 0.0; }
+
+size_t t2s2_adjoint_state_bytes(const t2s2_ctx* c) {
+  if (!c) return 0;
+  return static_cast<size_t>(kQ) * c->sp.plane * adjoint_real_bytes(c->cfg.storage);
+}
+
+size_t t2s2_adjoint_scratch_bytes(const t2s2_ctx* c) {
+  if (!c) return 0;
+  return 5 * align256(t2s2_adjoint_state_bytes(c)) + align256(t2s2_state_bytes(c)) +
+         align256(2 * kDiagBlocks * sizeof(double));
+}
+
+int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (c->sp.has_force) return fail(T2S2_ERR_UNSUPPORTED, "the adjoint covers unforced flows");
+  if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255))
+    return fail(T2S2_ERR_INVALID_ARG, "scratch must be a 256-byte aligned device pointer");
+  AdjParams& a = c->adj;
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.pitch = c->pitch;
+  a.plane = c->sp.plane;
+  a.per_x = c->sp.per_x;
+  a.per_y = c->sp.per_y;
+  a.wx = c->sp.wx;
+  a.wy = c->sp.wy;
+  a.wx32 = c->sp.wx32;
+  a.wy32 = c->sp.wy32;
+  const double A = c->cfg.A, w = c->omega;
+  a.A = A;
+  a.cPg = c->sp.cPg;
+  a.cPe = c->sp.cPe;
+  a.cQg = c->sp.cQg;
+  a.cQe = c->sp.cQe;
+  a.cRs = c->sp.cRs;
+  a.cRe = c->sp.cRe;
+  // d/d omega of (2 - A w)/(2 + w), (2 - w)/(2 + w) and 2/(2 + A w); the
+  // equilibrium coefficients are one minus these.
+  a.dcPg = -2.0 * (1.0 + A) / ((2.0 + w) * (2.0 + w));
+  a.dcQg = -4.0 / ((2.0 + w) * (2.0 + w));
+  a.dcRs = -2.0 * A / ((2.0 + A * w) * (2.0 + A * w));
+  for (int k = 0; k < 4; ++k) {
+    a.uw[k][0] = c->sp.uw[k][0];
+    a.uw[k][1] = c->sp.uw[k][1];
+  }
+  char* p = static_cast<char*>(scratch);
+  const size_t ab = align256(t2s2_adjoint_state_bytes(c));
+  a.P = p;
+  a.S = p + ab;
+  a.mu = p + 2 * ab;
+  a.lamR = p + 3 * ab;
+  a.lamS = p + 4 * ab;
+  a.next = p + 5 * ab;
+  c->adj_partial = reinterpret_cast<double*>(p + 5 * ab + align256(t2s2_state_bytes(c)));
+  c->adj_bound = true;
+  return T2S2_OK;
+}
+
+static int adj_ready(t2s2_ctx* c) {
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound || !c->adj_bound) return fail(T2S2_ERR_NOT_BOUND, "adjoint scratch not bound");
+  return T2S2_OK;
+}
+
+int t2s2_adjoint_seed_velocity(t2s2_ctx* c, const void* state, const double* gu,
+                               const double* gv, void* lam) {
+  g_last_error.clear();
+  if (int rc = adj_ready(c)) return rc;
+  if (!state || !lam) return fail(T2S2_ERR_INVALID_ARG, "NULL state or adjoint");
+  hipError_t e = launch_adjoint_seed(c->cfg.storage, c->adj, state, gu, gv, lam, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint_seed_velocity");
+  return T2S2_OK;
+}
+
+int t2s2_adjoint_step(t2s2_ctx* c, const void* state_n, const void* lam_np1, void* lam_n,
+                      double* domega_accum) {
+  g_last_error.clear();
+  if (int rc = adj_ready(c)) return rc;
+  if (!state_n || !lam_np1 || !lam_n || lam_np1 == lam_n)
+    return fail(T2S2_ERR_INVALID_ARG, "need a state and two distinct adjoint buffers");
+  hipError_t e = launch_adjoint_step(c->cfg.storage, c->adj, c->sp, c->grid, state_n, lam_np1,
+                                     lam_n, c->adj_partial, domega_accum, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint_step");
+  return T2S2_OK;
+}
+
+int t2s2_adjoint_init_macro(t2s2_ctx* c, const void* lam0, const double* rho, const double* ux,
+                            const double* uy, double* grho, double* gux, double* guy) {
+  g_last_error.clear();
+  if (int rc = adj_ready(c)) return rc;
+  if (!lam0 || !rho || !ux || !uy) return fail(T2S2_ERR_INVALID_ARG, "NULL input");
+  hipError_t e = launch_adjoint_init(c->cfg.storage, c->adj, lam0, rho, ux, uy, grho, gux, guy,
+                                     c->stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint_init_macro");
+  return T2S2_OK;
+}
+
+int t2s2_adjoint_read(t2s2_ctx* c, const void* lam, double* out) {
+  g_last_error.clear();
+  if (int rc = adj_ready(c)) return rc;
+  if (!lam || !out) return fail(T2S2_ERR_INVALID_ARG, "NULL buffer");
+  hipError_t e = launch_adjoint_convert(c->cfg.storage, c->adj, lam, out, nullptr, nullptr,
+                                        c->stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint_read");
+  return T2S2_OK;
+}
+
+int t2s2_adjoint_load(t2s2_ctx* c, const double* in, void* lam) {
+  g_last_error.clear();
+  if (int rc = adj_ready(c)) return rc;
+  if (!lam || !in) return fail(T2S2_ERR_INVALID_ARG, "NULL buffer");
+  hipError_t e = launch_adjoint_convert(c->cfg.storage, c->adj, nullptr, nullptr, in, lam,
+                                        c->stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint_load");
   return T2S2_OK;
 }
 

@@ -1,0 +1,177 @@
+// Device helpers shared by the step and adjoint kernels: the D2Q9 lattice,
+// storage conversions, the equilibrium and its neighbours.  Internal linkage
+// (anonymous namespace) in every translation unit that includes it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "t2s2_internal.h"
+
+namespace t2s2 {
+namespace {
+
+__host__ __device__ constexpr int ex_of(int q) {
+  return (q == 1 || q == 5 || q == 8) ? 1 : ((q == 3 || q == 6 || q == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int ey_of(int q) {
+  return (q == 2 || q == 5 || q == 6) ? 1 : ((q == 4 || q == 7 || q == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr double w_of(int q) {
+  return q == 0 ? 4.0 / 9.0 : (q < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+template <typename S>
+struct Cvt;
+template <>
+struct Cvt<double> {
+  using R = double;
+  __device__ static double ld(double v) { return v; }
+  __device__ static double st(double v) { return v; }
+};
+template <>
+struct Cvt<float> {
+  using R = float;
+  __device__ static float ld(float v) { return v; }
+  __device__ static float st(float v) { return v; }
+};
+// BF16 as raw bits: widening is a 16-bit shift; narrowing rounds to nearest
+// even by adding 0x7fff plus the lowest kept bit before truncating (NaN kept
+// quiet).
+struct Bf16 {
+  unsigned short bits;
+};
+template <>
+struct Cvt<Bf16> {
+  using R = float;
+  __device__ static float ld(Bf16 v) { return __uint_as_float(static_cast<unsigned>(v.bits) << 16); }
+  __device__ static Bf16 st(float v) {
+    const unsigned u = __float_as_uint(v);
+    if (v != v) return Bf16{static_cast<unsigned short>((u >> 16) | 0x40u)};
+    return Bf16{static_cast<unsigned short>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16)};
+  }
+};
+template <>
+struct Cvt<_Float16> {
+  using R = float;
+  __device__ static float ld(_Float16 v) { return static_cast<float>(v); }
+  __device__ static _Float16 st(float v) { return static_cast<_Float16>(v); }  // RNE
+};
+
+__device__ inline int wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+__device__ inline int clampi(int i, int lo, int hi) { return i < lo ? lo : (i > hi ? hi : i); }
+
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (each squares the relative error), for the one division per node.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// f^eq_q - w_q = w_q (drho + rho X_q),  X_q = 3 e + 9/2 e^2 - 3/2 |u|^2,
+// e = xi_q . u  (eq 3.2 with c_s^2 = 1/3).
+template <typename Real>
+__device__ inline void feq_dev(double drho, double rho, double ux, double uy, Real out[kQ]) {
+  const Real d = static_cast<Real>(drho), r = static_cast<Real>(rho);
+  const Real x = static_cast<Real>(ux), y = static_cast<Real>(uy);
+  const Real uu = Real(1.5) * (x * x + y * y);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const Real e = Real(ex_of(q)) * x + Real(ey_of(q)) * y;
+    const Real X = e * (Real(3) + Real(4.5) * e) - uu;
+    out[q] = Real(w_of(q)) * (d + r * X);
+  }
+}
+
+// Guo force term (eq 3.12): F_q = (F . (xi_q - u)) f^eq_q / c_s^2.
+template <typename Real>
+__device__ inline void force_terms(double Fx, double Fy, double ux, double uy,
+                                   const Real feq[kQ], Real out[kQ]) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const Real fu = static_cast<Real>(Fx * (ex_of(q) - ux) + Fy * (ey_of(q) - uy));
+    out[q] = Real(3) * fu * (Real(w_of(q)) + feq[q]);
+  }
+}
+
+// Moment sums in FP64 in the fixed order q = 0..8.
+template <typename Real>
+__device__ inline void moment_sums(const Real a[kQ], double& s, double& jx, double& jy) {
+  s = 0.0;
+  jx = 0.0;
+  jy = 0.0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const double v = static_cast<double>(a[q]);
+    s += v;
+    if (ex_of(q) > 0) jx += v;
+    if (ex_of(q) < 0) jx -= v;
+    if (ey_of(q) > 0) jy += v;
+    if (ey_of(q) < 0) jy -= v;
+  }
+}
+
+// f^eq(rho, u_b) - f^eq(rho, u_f) (the non-equilibrium extrapolation shift
+// of eq 3.10, with rho taken at the fluid node).
+template <typename Real>
+__device__ inline void nee_shift(double rho, double uxf, double uyf, double uxb, double uyb,
+                                 Real out[kQ]) {
+  const Real r = static_cast<Real>(rho);
+  const Real xf = static_cast<Real>(uxf), yf = static_cast<Real>(uyf);
+  const Real xb = static_cast<Real>(uxb), yb = static_cast<Real>(uyb);
+  const Real uuf = Real(1.5) * (xf * xf + yf * yf), uub = Real(1.5) * (xb * xb + yb * yb);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const Real ef = Real(ex_of(q)) * xf + Real(ey_of(q)) * yf;
+    const Real eb = Real(ex_of(q)) * xb + Real(ey_of(q)) * yb;
+    const Real Xf = ef * (Real(3) + Real(4.5) * ef) - uuf;
+    const Real Xb = eb * (Real(3) + Real(4.5) * eb) - uub;
+    out[q] = Real(w_of(q)) * r * (Xb - Xf);
+  }
+}
+
+__device__ inline void wall_velocity(const StepParams& p, int c, int r, double& ub,
+                                     double& vb) {
+  int side;
+  if (!p.per_x && c == 0)
+    side = 0;
+  else if (!p.per_x && c == p.nx - 1)
+    side = 1;
+  else if (!p.per_y && r == 0)
+    side = 2;
+  else
+    side = 3;
+  ub = p.uw[side][0];
+  vb = p.uw[side][1];
+}
+
+template <typename Real>
+__device__ inline const Real* weights_x(const StepParams& p);
+template <>
+__device__ inline const double* weights_x<double>(const StepParams& p) {
+  return p.wx;
+}
+template <>
+__device__ inline const float* weights_x<float>(const StepParams& p) {
+  return p.wx32;
+}
+template <typename Real>
+__device__ inline const Real* weights_y(const StepParams& p);
+template <>
+__device__ inline const double* weights_y<double>(const StepParams& p) {
+  return p.wy;
+}
+template <>
+__device__ inline const float* weights_y<float>(const StepParams& p) {
+  return p.wy32;
+}
+
+}  // namespace
+}  // namespace t2s2

@@ -61,6 +61,28 @@ struct AuxParams {
   const double* jy;     // [ny]
 };
 
+// Adjoint of the step (t2s2_adjoint.hip).  Real-typed buffers (FP64 for
+// T2S2_F64 storage, FP32 otherwise) share the state's pitched layout.
+struct AdjParams {
+  int nx, ny;
+  long long pitch, plane;
+  int per_x, per_y;
+  const double* wx;
+  const double* wy;
+  const float* wx32;
+  const float* wy32;
+  double A;
+  double cPg, cPe, cQg, cQe, cRs, cRe;
+  double dcPg, dcQg, dcRs;  // d/d omega of cPg, cQg, cRs
+  double uw[4][2];
+  void* P;     // P, then the adjoint of P
+  void* S;     // S
+  void* mu;    // adjoint of the interior output (= adjoint of Q)
+  void* lamR;  // adjoint of R
+  void* lamS;  // adjoint of S
+  void* next;  // f~^{n+1} recomputed (storage type)
+};
+
 constexpr int kDiagBlocks = 512;
 constexpr int kDiagSlots = 8;
 
@@ -81,5 +103,19 @@ hipError_t launch_diagnostics(int storage, const AuxParams& a, const void* state
                               double* partials, double* result, hipStream_t s);
 
 size_t storage_bytes(int storage);
+
+// Adjoint launchers (t2s2_adjoint.hip).
+size_t adjoint_real_bytes(int storage);
+hipError_t launch_adjoint_step(int storage, const AdjParams& a, const StepParams& sp,
+                               int step_grid, const void* state_n, const void* lam_np1,
+                               void* lam_n, double* partial, double* accum, hipStream_t s);
+hipError_t launch_adjoint_seed(int storage, const AdjParams& a, const void* state,
+                               const double* gu, const double* gv, void* lam, hipStream_t s);
+hipError_t launch_adjoint_init(int storage, const AdjParams& a, const void* lam,
+                               const double* rho, const double* ux, const double* uy,
+                               double* grho, double* gux, double* guy, hipStream_t s);
+hipError_t launch_adjoint_convert(int storage, const AdjParams& a, const void* lam,
+                                  double* dense, const double* dense_in, void* lam_out,
+                                  hipStream_t s);
 
 }  // namespace t2s2

@@ -1,0 +1,186 @@
+"""GPU adjoint: per-step dot-product test, agreement with the oracle twin's
+autograd, and the sqrt(N)-checkpointed rollout gradient against central
+finite differences (FP64)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+t2s2 = pytest.importorskip("paper_1911_12913_amd")
+from paper_1911_12913_amd.rollout import RolloutSpec, T2S2Rollout, forward_velocity  # noqa: E402
+
+
+def _spec(case, nsteps, storage="f64", checkpoint_every=None):
+    return RolloutSpec(x=case.x, y=case.y, periodic_x=case.periodic_x,
+                       periodic_y=case.periodic_y, period_x=case.period_x,
+                       period_y=case.period_y, cfl=case.cfl, dt=case.dt or 0.0, eta=case.eta,
+                       A=case.A, u_wall=case.u_wall, storage=storage, nsteps=nsteps,
+                       checkpoint_every=checkpoint_every, device="cuda:0")
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a), dtype=torch.float64, device="cuda:0")
+
+
+@pytest.mark.parametrize("kind", ["cavity", "tgv"])
+def test_adjoint_step_dot_product(kind):
+    """<J v, w> = <v, J^T w> for one step: J v by central differences of the
+    GPU step, J^T w by the hand-written adjoint step."""
+    if kind == "cavity":
+        case = W.cavity_case(40, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=1e-3, seed=1)
+    else:
+        case = W.tgv_case(48, 40, u0=0.05, nu=0.01, cfl=0.6, eta=0.05)
+    print(f"[gpu] adjoint dot product {kind}", flush=True)
+    ctx = t2s2.context_for_case(case)
+    ctx.enable_adjoint()
+    g0 = oracle.run(case, oracle.init(case), 20)
+    v = W.random_state(g0.shape, 1.0, 21)
+    w = W.random_state(g0.shape, 1.0, 22)
+    eps = 1e-6 * np.abs(g0).max()
+
+    def step_from(g):
+        ctx.init_distributions(torch.from_numpy(g))
+        ctx.step(1)
+        return ctx.read_distributions().cpu().numpy()
+
+    jv = (step_from(g0 + eps * v) - step_from(g0 - eps * v)) / (2 * eps)
+    ctx.init_distributions(torch.from_numpy(g0))
+    state = ctx.save_state()
+    lam_w = ctx.adjoint_load(w)
+    lam_out = ctx.adjoint_buffer()
+    ctx.adjoint_step(state, lam_w, lam_out)
+    jtw = ctx.adjoint_read(lam_out).cpu().numpy()
+    lhs, rhs = float(np.sum(jv * w)), float(np.sum(v * jtw))
+    print(f"    <Jv,w> {lhs:.12e}  <v,J^T w> {rhs:.12e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+
+
+def test_adjoint_matches_oracle_twin_autograd():
+    """Gradients of a probe loss after 40 steps of a 33x33 cavity w.r.t. the
+    initial velocity field and nu: GPU adjoint vs autograd through the
+    oracle's torch twin."""
+    from oracle.twin import Twin
+
+    case = W.cavity_case(32, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=0.0)
+    nsteps = 40
+    ux0, uy0 = W.gaussian_velocity(case.nx, case.ny, std=1e-3, seed=1)
+    rho0 = np.ones((case.ny, case.nx))
+    probes = W.probe_nodes(case.nx, case.ny, 16, seed=2)
+    ut = W.random_state((2, 16), 0.02, 5)
+
+    # oracle twin + autograd
+    tw = Twin(case)
+    tu = torch.tensor(ux0, requires_grad=True)
+    tv = torch.tensor(uy0, requires_grad=True)
+    tnu = torch.tensor(case.nu, dtype=torch.float64, requires_grad=True)
+    phi = tw.run(tw.init(torch.tensor(rho0), tu, tv), tnu, nsteps)
+    _, _, u, v = Twin.moments(phi)
+    pj, pi = torch.as_tensor(probes[:, 1]), torch.as_tensor(probes[:, 0])
+    loss = ((u[pj, pi] - torch.tensor(ut[0])) ** 2 + (v[pj, pi] - torch.tensor(ut[1])) ** 2).mean()
+    loss.backward()
+
+    # GPU rollout + hand-written adjoint
+    spec = _spec(case, nsteps, checkpoint_every=7)
+    gu = _dev(ux0).requires_grad_(True)
+    gv = _dev(uy0).requires_grad_(True)
+    gnu = torch.tensor(case.nu, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    U, V = T2S2Rollout.apply(_dev(rho0), gu, gv, gnu, spec)
+    pjd, pid = pj.to("cuda:0"), pi.to("cuda:0")
+    loss_g = ((U[pjd, pid] - _dev(ut[0])) ** 2 + (V[pjd, pid] - _dev(ut[1])) ** 2).mean()
+    loss_g.backward()
+    e_loss = abs(loss_g.item() - loss.item()) / abs(loss.item())
+    e_u = W.rel_l2(gu.grad.cpu().numpy(), tu.grad.numpy())
+    e_v = W.rel_l2(gv.grad.cpu().numpy(), tv.grad.numpy())
+    e_nu = abs(gnu.grad.item() - tnu.grad.item()) / abs(tnu.grad.item())
+    print(f"    loss {e_loss:.2e}  dL/du0 {e_u:.2e}  dL/dv0 {e_v:.2e}  dL/dnu {e_nu:.2e}",
+          flush=True)
+    assert e_loss < 1e-11 and e_u < 1e-9 and e_v < 1e-9 and e_nu < 1e-9
+
+
+def _cavity513():
+    """Differentiation workload: cavity on the 513 x 513 stretched mesh, Re 400."""
+    return W.cavity_case(512, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=0.0)
+
+
+def _probe_loss_fn(case, nsteps, storage):
+    """Loss = mean over 64 seeded interior probes of |u - u_target|^2, the
+    targets from a reference run with nu_ref = 1.05 nu and no initial
+    perturbation."""
+    probes = W.probe_nodes(case.nx, case.ny, 64, seed=2)
+    pj = torch.as_tensor(probes[:, 1], device="cuda:0")
+    pi = torch.as_tensor(probes[:, 0], device="cuda:0")
+    zero = np.zeros((case.ny, case.nx))
+    rho0 = _dev(np.ones((case.ny, case.nx)))
+    spec = _spec(case, nsteps, storage=storage)
+    ut, vt = forward_velocity(spec, rho0, _dev(zero), _dev(zero), 1.05 * case.nu)
+    ut, vt = ut[pj, pi].clone(), vt[pj, pi].clone()
+
+    def loss_of(U, V):
+        return ((U[pj, pi] - ut) ** 2 + (V[pj, pi] - vt) ** 2).mean()
+
+    return spec, rho0, loss_of
+
+
+@pytest.mark.parametrize("nsteps", [2000])
+def test_rollout_gradient_vs_central_differences_fp64(nsteps):
+    """dL/dnu and the directional derivative along a seeded direction of the
+    initial velocity, adjoint vs Richardson-extrapolated central differences,
+    FP64, 513x513 cavity, Re 400, CFL 0.9, N = 2000 with sqrt(N)
+    checkpoints: relative agreement 1e-6."""
+    case = _cavity513()
+    print(f"[gpu] rollout gradient 513x513, {nsteps} steps", flush=True)
+    spec, rho0, loss_of = _probe_loss_fn(case, nsteps, "f64")
+    u0, v0 = W.gaussian_velocity(case.nx, case.ny, std=1e-3, seed=1)
+    du, dv = W.gaussian_velocity(case.nx, case.ny, std=1e-3, seed=7)
+    gu = _dev(u0).requires_grad_(True)
+    gv = _dev(v0).requires_grad_(True)
+    gnu = torch.tensor(case.nu, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    U, V = T2S2Rollout.apply(rho0, gu, gv, gnu, spec)
+    L0 = loss_of(U, V)
+    L0.backward()
+    adj_dir = float(torch.sum(gu.grad * _dev(du)) + torch.sum(gv.grad * _dev(dv)))
+    adj_nu = gnu.grad.item()
+
+    def L_at(s_dir, nu):
+        U, V = forward_velocity(spec, rho0, _dev(u0 + s_dir * du), _dev(v0 + s_dir * dv), nu)
+        return loss_of(U, V).item()
+
+    def richardson(f, h):
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        return (4 * d2 - d1) / 3
+
+    fd_dir = richardson(lambda s: L_at(s, case.nu), 0.02)
+    fd_nu = richardson(lambda s: L_at(0.0, case.nu + s), 1e-3 * case.nu)
+    e_dir = abs(adj_dir - fd_dir) / abs(fd_dir)
+    e_nu = abs(adj_nu - fd_nu) / abs(fd_nu)
+    print(f"    L {L0.item():.6e}  dir adj {adj_dir:.10e} fd {fd_dir:.10e} rel {e_dir:.2e}",
+          flush=True)
+    print(f"    nu  adj {adj_nu:.10e} fd {fd_nu:.10e} rel {e_nu:.2e}", flush=True)
+    assert e_dir < 1e-6 and e_nu < 1e-6
+
+
+def test_fp32_adjoint_against_fp64_adjoint():
+    """The FP32 rollout gradient of the 513x513 workload, reported against the
+    FP64 one (200 steps)."""
+    case = _cavity513()
+    grads = {}
+    for storage in ("f64", "f32"):
+        spec, rho0, loss_of = _probe_loss_fn(case, 200, storage)
+        u0, v0 = W.gaussian_velocity(case.nx, case.ny, std=1e-3, seed=1)
+        gu = _dev(u0).requires_grad_(True)
+        gv = _dev(v0).requires_grad_(True)
+        gnu = torch.tensor(case.nu, dtype=torch.float64, device="cuda:0", requires_grad=True)
+        U, V = T2S2Rollout.apply(rho0, gu, gv, gnu, spec)
+        loss_of(U, V).backward()
+        grads[storage] = (gu.grad.cpu().numpy(), gv.grad.cpu().numpy(), gnu.grad.item())
+    e_u = W.rel_l2(np.stack(grads["f32"][:2]), np.stack(grads["f64"][:2]))
+    e_nu = abs(grads["f32"][2] - grads["f64"][2]) / abs(grads["f64"][2])
+    print(f"    FP32 vs FP64 adjoint: dL/du0 rel L2 {e_u:.2e}, dL/dnu rel {e_nu:.2e}", flush=True)
+    assert e_u < 1e-2 and e_nu < 1e-2
