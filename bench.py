@@ -12,7 +12,12 @@ A step is one full time step of the grid (one launch of the fused kernel).
 Prints one JSON line: MLUPS (lattice-node updates per second, all nodes),
 the roofline of the fused step kernel (algorithmic bytes per launch / the
 launch time measured with HIP events on the launch stream), and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+CPU oracle timed on a bounded sample of the same workload.  The precision
+forms (deviations stored in FP32, BF16 or FP16, FP32 arithmetic, FP64
+moment sums) then run the same steps on the same grid; each reports its
+MLUPS, its speed-up over the FP64 line and the relative L2 error of its
+final velocity field against the FP64 result (which matches the oracle to
+round-off) and against the closed-form decay of eq 3.4.
 """
 from __future__ import annotations
 
@@ -31,8 +36,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 BYTES_PER_NODE = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36}
 METRIC = "D2Q9 MLUPS & % HBM peak, FP64 vs FP32/BF16-store at stated L2 error"
 KERNEL_SOURCES = ["paper_1911_12913_amd/csrc/t2s2_kernels.hip",
+                  "paper_1911_12913_amd/csrc/t2s2_device.h",
                   "paper_1911_12913_amd/csrc/t2s2_internal.h",
-                  "paper_1911_12913_amd/csrc/t2s2_api.hip"]
+                  "paper_1911_12913_amd/csrc/t2s2_api.hip",
+                  "paper_1911_12913_amd/build.py"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_tgv4096.json")
 
 
@@ -64,26 +71,46 @@ def tgv_case(n, nu, cfl, eta):
     return W.tgv_case(n, n, u0=0.01, nu=nu, cfl=cfl, eta=eta)
 
 
-def gpu_leg(args, case):
+def W_tgv_fields(case, t):
+    import workloads as W
+
+    m = case.meta
+    return W.tgv_fields(case.x, case.y, m["k1"], m["k2"], m["u0"], case.nu, t)
+
+
+def gpu_leg(case, storage, steps, warmup):
+    """One storage form on the GPU: warmup steps, then `steps` timed steps
+    between two HIP events recorded on the library's launch stream.  Returns
+    the elapsed ms, the diagnostics, dt and the final velocity fields."""
     import torch
 
     import paper_1911_12913_amd as t2s2
 
     torch.cuda.set_device(0)
-    ctx = t2s2.context_for_case(case, storage=args.storage, device="cuda:0")
+    ctx = t2s2.context_for_case(case, storage=storage, device="cuda:0")
     ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
-    ctx.step(args.warmup)
+    ctx.step(warmup)
     torch.cuda.synchronize()
     stream = ctx.stream
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record(stream)
-    ctx.step(args.steps)
+    ctx.step(steps)
     stop.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
     diag = ctx.diagnostics()
-    return ms, diag, ctx.dt
+    _, ux, uy = ctx.moments()
+    torch.cuda.synchronize()
+    dt = ctx.dt
+    ctx.close()
+    return ms, diag, dt, torch.stack([ux, uy])
+
+
+def rel_l2_dev(a, b) -> float:
+    import torch
+
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
 def cpu_leg(case, steps, threads):
@@ -107,6 +134,9 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=4096, help="grid side")
     ap.add_argument("--storage", default="f64", choices=sorted(BYTES_PER_NODE))
     ap.add_argument("--nu", type=float, default=1e-4)
+    ap.add_argument("--forms", default="f32,bf16,f16",
+                    help="reduced-storage forms run after the headline one, each with the "
+                         "same steps; their speed-up and velocity error are reported")
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="oracle steps timed on the host (0 = skip)")
     ap.add_argument("--cpu-threads", type=int, default=None)
@@ -123,7 +153,7 @@ def main(argv=None):
     n, nu, cfl, eta = args.n, args.nu, 0.9, 0.01
     case = tgv_case(n, nu, cfl, eta)
     nodes = n * n
-    ms, diag, dt = gpu_leg(args, case)
+    ms, diag, dt, vel = gpu_leg(case, args.storage, args.steps, args.warmup)
     if args.copy_bytes > 0:
         import torch
 
@@ -139,6 +169,28 @@ def main(argv=None):
     bytes_launch = BYTES_PER_NODE[args.storage] * nodes
     achieved = bytes_launch / (ms_step * 1e-3) / 1e9
     traffic = measured_traffic(args.storage)
+
+    # closed-form velocity (eq 3.4) at the final time, for every form's error
+    import torch
+
+    t_end = (args.warmup + args.steps) * dt
+    _, ue, ve, _ = W_tgv_fields(case, t_end)
+    exact = torch.stack([torch.from_numpy(ue), torch.from_numpy(ve)]).to("cuda:0")
+    gre = rel_l2_dev(vel, exact)
+
+    forms = {}
+    for st in [f for f in args.forms.split(",") if f and f != args.storage]:
+        ms_f, diag_f, _, vel_f = gpu_leg(case, st, args.steps, args.warmup)
+        v_f = nodes * args.steps / (ms_f * 1e-3) / 1e6
+        bl = BYTES_PER_NODE[st] * nodes / (ms_f / args.steps * 1e-3) / 1e9
+        forms[st] = {"value": v_f, "unit": "MLUPS", "ms_per_step": ms_f / args.steps,
+                     "speedup_vs_headline": v_f / mlups,
+                     "rel_l2_velocity_vs_headline": rel_l2_dev(vel_f, vel),
+                     "rel_l2_velocity_vs_closed_form": rel_l2_dev(vel_f, exact),
+                     "hbm_frac": bl / HBM_PEAK_GBS, "bytes_per_node": BYTES_PER_NODE[st],
+                     "traffic": measured_traffic(st), "nonfinite": diag_f["nonfinite"]}
+        del vel_f
+    del exact
 
     cpu = None
     if args.cpu_steps > 0:
@@ -169,6 +221,8 @@ def main(argv=None):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "step_kernel", "bytes_per_node": BYTES_PER_NODE[args.storage]},
         "cpu_baseline": cpu,
+        "rel_l2_velocity_vs_closed_form": gre,
+        "precision_forms": forms,
         "diagnostics_after": {k: diag[k] for k in ("kinetic_energy", "max_speed", "nonfinite")},
     }
     print(json.dumps(rec), flush=True)

@@ -236,6 +236,7 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   // at bind time from the device's CU count and the kernel's occupancy.
   p.nstrips = (nx + kStripOut - 1) / kStripOut;
   p.nblocks = 8;
+  p.band = ny;
   c->grid = 8;
 
   size_t off = 0;
@@ -330,6 +331,10 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   nb = std::max<long long>(8, nb / 8 * 8);
   nb = std::min<long long>(nb, std::max<long long>(8, rows / 8 * 8));
   c->sp.nblocks = static_cast<int>(nb);
+  // Band height = one block's share, so that (away from the last band) each
+  // block owns exactly one strip of one band and the blocks of neighbouring
+  // strips march the same rows at the same time.
+  c->sp.band = static_cast<int>(std::min<long long>(c->ny, std::max<long long>(1, (rows + nb - 1) / nb)));
   c->grid = static_cast<int>(nb);
   c->bound = true;
   c->cur = 0;

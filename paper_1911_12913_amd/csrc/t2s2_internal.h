@@ -38,6 +38,7 @@ struct StepParams {
   int per_x, per_y;
   int nstrips;  // strips of kStripOut output columns
   int nblocks;  // equal ranges of the nstrips * ny strip-rows, one per block
+  int band;     // rows per band of the band-major strip-row order
   const double* wx;   // [nx][2][4] dt-scaled x weights (FP64)
   const double* wy;   // [ny][2][4]
   const float* wx32;  // same in FP32

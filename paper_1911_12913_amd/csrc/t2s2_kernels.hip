@@ -116,6 +116,10 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
   using Real = typename Cvt<Store>::R;
   __shared__ Real ringP[kRing * kQ * kLanes];       // [slot][q][lane]
   __shared__ Real ringR[kRing * (kQ - 1) * kLanes];  // [slot][q-1][lane]
+  // R of the top wall row ny-1, kept out of the ring: it is written (eq 3.10)
+  // by the wave that computes row ny-2, in the same phase in which the ring
+  // slot of row ny-1 still holds row ny-9 for the output row ny-7.
+  __shared__ Real topR[kWalls ? (kQ - 1) * kLanes : 1];
 
   const int lane = threadIdx.x & (kLanes - 1);
   const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
@@ -126,25 +130,37 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
 
   for (int i = threadIdx.x; i < kRing * kQ * kLanes; i += kBlockThreads) ringP[i] = Real(0);
   for (int i = threadIdx.x; i < kRing * (kQ - 1) * kLanes; i += kBlockThreads) ringR[i] = Real(0);
+  if (kWalls)
+    for (int i = threadIdx.x; i < (kQ - 1) * kLanes; i += kBlockThreads) topR[i] = Real(0);
 
-  // Work: the strips laid end to end form nstrips * ny strip-rows, cut into
-  // nblocks equal ranges (one per block, so every block does the same
-  // work).  A range may run over a strip boundary; each piece is marched
-  // separately.  XCD-aware order: the grid is a multiple of 8 and blocks are
-  // dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8; each XCD
-  // gets a contiguous run of ranges, which keeps a strip's consecutive
-  // segments and its neighbouring strips in one L2.
+  // Work: the rows are cut into bands of p.band rows; the strip-rows are
+  // ordered band by band, strip by strip within a band, row by row within a
+  // strip, and this order is cut into nblocks equal ranges (one per block,
+  // so every block does the same work).  With the band height equal to one
+  // block's share, a block owns one strip of one band, and the blocks of
+  // neighbouring strips start on the same row and march in step: the cache
+  // lines that two strips share (the halo columns) are fetched from HBM once
+  // and found in L2 by the second strip.  A range may run over a strip or
+  // band boundary; each piece is marched separately.  XCD-aware order: the
+  // grid is a multiple of 8 and blocks are dealt round-robin to the 8 XCDs,
+  // so block b runs on XCD b % 8; each XCD gets a contiguous run of ranges,
+  // i.e. neighbouring strips of a band share one L2.
   const int G = gridDim.x;
   const int L = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
   if (L >= p.nblocks) return;  // padding block: whole block, before any barrier
   const long long total = static_cast<long long>(p.nstrips) * ny;
+  const long long band_pieces = static_cast<long long>(p.nstrips) * p.band;
   long long beg = total * L / p.nblocks;
   const long long end = total * (L + 1) / p.nblocks;
 
   while (beg < end) {  // uniform per block
-    const int strip = static_cast<int>(beg / ny);
-    const int y0 = static_cast<int>(beg % ny);
-    const int y1 = static_cast<int>(min(static_cast<long long>(ny), y0 + (end - beg)));
+    const int b = static_cast<int>(beg / band_pieces);
+    const long long rem = beg - b * band_pieces;
+    const int r0 = b * p.band;
+    const int hb = min(p.band, ny - r0);  // the last band may be shorter
+    const int strip = static_cast<int>(rem / hb);
+    const int y0 = r0 + static_cast<int>(rem % hb);
+    const int y1 = static_cast<int>(min(static_cast<long long>(r0 + hb), y0 + (end - beg)));
     beg += y1 - y0;
 
     const int x0 = strip * kStripOut;
@@ -295,7 +311,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
                   wall_velocity(p, c + dx, r + dy, ub, vb);
                   Real sh[kQ];
                   nee_shift(rho, ux, uy, ub, vb, sh);
-                  Real* slotW = ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
+                  Real* slotW = dy == 1 ? topR : ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
 #pragma unroll
                   for (int q = 1; q < kQ; ++q)
                     slotW[(q - 1) * kLanes + lane + dx] = R[q] + sh[q];
@@ -317,8 +333,10 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
           row_weights(weights_y<Real>(p), o, wyr);
           const Real* rb[5];
 #pragma unroll
-          for (int k = 0; k < 5; ++k)
+          for (int k = 0; k < 5; ++k) {
             rb[k] = ringR + ((o + k - 2) & (kRing - 1)) * (kQ - 1) * kLanes + lane;
+            if (kWalls && !p.per_y && o + k - 2 == ny - 1) rb[k] = topR + lane;
+          }
           Real out[kQ];
           out[0] = qold[0];
 #pragma unroll

@@ -69,11 +69,14 @@ def test_cavity65_seeded_matches_oracle():
     _compare(case, g, d, u, v, ref)
 
 
-@pytest.mark.parametrize("blocks", ["8", "24", "64"])
+@pytest.mark.parametrize("blocks", ["8", "16", "24", "40", "48", "64"])
 def test_cavity_ragged_many_tiles(blocks, monkeypatch):
     """Non-square cavity spanning 3 strips (130 columns: 56 + 56 + 18) cut
     into 8 to 64 block ranges, so ranges start mid-strip and run across strip
-    boundaries; ragged last strip."""
+    and band boundaries; ragged last strip.  Across these block counts the
+    pieces that hold row ny-7 start at every row residue (ny - y0) mod 4, so
+    each of the four waves in turn computes row ny-2 and writes the top-wall
+    R row while row ny-7 is being output (a ring-slot hazard once)."""
     monkeypatch.setenv("T2S2_BLOCKS", blocks)
     case = W.cavity_case(64, lid=0.1, re=400.0, cfl=0.8, eta=0.1, noise=1e-6, seed=3)
     x = W.tanh_walled(129, 1.5)
