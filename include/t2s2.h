@@ -78,7 +78,10 @@ typedef struct t2s2_ctx t2s2_ctx;
  * strictly increasing; on a walled axis the first and last nodes are walls;
  * on a periodic axis x[nx-1] - x[0] < period).  Validates nx, ny >= 5,
  * 0 < cfl <= 1 (unless dt > 0), nu > 0, 0 <= eta <= 1, 0 <= A <= 1, and
- * computes dt and the stencil coefficients on the host.  No device call. */
+ * computes dt and the stencil coefficients on the host.  One population
+ * plane (ny * pitch elements of the storage type) must be under 4 GiB
+ * (T2S2_ERR_UNSUPPORTED otherwise; FP64 up to about 23000 x 23000 nodes).
+ * No device call. */
 int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y, int ny,
                 t2s2_ctx** out);
 

@@ -170,6 +170,10 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   if (!(cfg->A >= 0.0 && cfg->A <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "A not in [0,1]");
   if (cfg->storage < T2S2_F64 || cfg->storage > T2S2_F16_DEV)
     return fail(T2S2_ERR_INVALID_ARG, "unknown storage");
+  // The step kernel addresses a population plane with 32-bit byte offsets.
+  if (static_cast<long long>(ny) * ((nx + 63) / 64 * 64) *
+          static_cast<long long>(storage_bytes(cfg->storage)) >= (1LL << 32))
+    return fail(T2S2_ERR_UNSUPPORTED, "one population plane (ny * pitch elements) must be under 4 GiB");
   if (!std::isfinite(cfg->force[0]) || !std::isfinite(cfg->force[1]))
     return fail(T2S2_ERR_INVALID_ARG, "force not finite");
   for (int s = 0; s < 4; ++s)
@@ -215,6 +219,27 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   p.cRs = 2.0 / (2.0 + A * w);
   p.cRe = A * w / (2.0 + A * w);
   p.cRF = A * dt / (2.0 + A * w);
+  {
+    const double wc[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
+    p.c64.cPg = p.cPg;
+    p.c64.cQg = p.cQg;
+    p.c64.cRs = p.cRs;
+    p.c64.A = A;
+    for (int k = 0; k < 3; ++k) {
+      p.c64.kP[k] = p.cPe * wc[k];
+      p.c64.kQ[k] = p.cQe * wc[k];
+      p.c64.kR[k] = p.cRe * wc[k];
+    }
+    p.c32.cPg = static_cast<float>(p.c64.cPg);
+    p.c32.cQg = static_cast<float>(p.c64.cQg);
+    p.c32.cRs = static_cast<float>(p.c64.cRs);
+    p.c32.A = static_cast<float>(A);
+    for (int k = 0; k < 3; ++k) {
+      p.c32.kP[k] = static_cast<float>(p.c64.kP[k]);
+      p.c32.kQ[k] = static_cast<float>(p.c64.kQ[k]);
+      p.c32.kR[k] = static_cast<float>(p.c64.kR[k]);
+    }
+  }
   p.half_dt = 0.5 * dt;
   p.half_h = 0.5 * A * dt;
   p.Fx = cfg->force[0];

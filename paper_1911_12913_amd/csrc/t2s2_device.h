@@ -101,21 +101,58 @@ __device__ inline void force_terms(double Fx, double Fy, double ux, double uy,
   }
 }
 
-// Moment sums in FP64 in the fixed order q = 0..8.
+// Moment sums in FP64, in a fixed order: the three populations moving in
+// +x, in -x, in +y and in -y are summed first, and the mass reuses the x
+// groups (14 additions).
 template <typename Real>
 __device__ inline void moment_sums(const Real a[kQ], double& s, double& jx, double& jy) {
-  s = 0.0;
-  jx = 0.0;
-  jy = 0.0;
+  double v[kQ];
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const double v = static_cast<double>(a[q]);
-    s += v;
-    if (ex_of(q) > 0) jx += v;
-    if (ex_of(q) < 0) jx -= v;
-    if (ey_of(q) > 0) jy += v;
-    if (ey_of(q) < 0) jy -= v;
-  }
+  for (int q = 0; q < kQ; ++q) v[q] = static_cast<double>(a[q]);
+  const double xp = v[1] + v[5] + v[8], xm = v[3] + v[6] + v[7];
+  const double yp = v[2] + v[5] + v[6], ym = v[4] + v[7] + v[8];
+  jx = xp - xm;
+  jy = yp - ym;
+  s = (v[0] + (v[2] + v[4])) + (xp + xm);
+}
+
+// Lattice-weight class of direction q: 0 rest, 1 axis, 2 diagonal.
+__host__ __device__ constexpr int wclass(int q) { return q == 0 ? 0 : (q < 5 ? 1 : 2); }
+
+// Density and velocity of eq 3.3 (without the force shift) from the FP64
+// moment sums.  FP64 arithmetic divides in FP64.  FP32 arithmetic rounds
+// the sums to FP32 and multiplies by the hardware reciprocal of rho refined
+// by one Newton step.
+__device__ inline void velocity(double s, double jx, double jy, double& r, double& x, double& y) {
+  r = 1.0 + s;
+  const double ir = recip(r);
+  x = jx * ir;
+  y = jy * ir;
+}
+__device__ inline void velocity(double s, double jx, double jy, float& r, float& x, float& y) {
+  r = 1.0f + static_cast<float>(s);
+  float ir = __builtin_amdgcn_rcpf(r);
+  ir = __builtin_fmaf(__builtin_fmaf(-r, ir, 1.0f), ir, ir);
+  x = static_cast<float>(jx) * ir;
+  y = static_cast<float>(jy) * ir;
+}
+
+// Brackets X_q of the equilibrium, f^eq_q - w_q = w_q (drho + rho X_q) with
+// X_q = 3 e_q + 9/2 e_q^2 - 3/2 |u|^2 and e_q = xi_q . u (eq 3.2, c_s^2 =
+// 1/3).  Opposite directions share 9/2 e^2 - 3/2 |u|^2.
+template <typename Real>
+__device__ inline void eq_brackets(Real x, Real y, Real X[kQ]) {
+  const Real uu = Real(1.5) * (x * x + y * y);
+  X[0] = -uu;
+  auto pair = [&](Real e, int qp, int qm) {
+    const Real T = (Real(4.5) * e) * e - uu;
+    X[qp] = T + Real(3) * e;
+    X[qm] = T - Real(3) * e;
+  };
+  pair(x, 1, 3);
+  pair(y, 2, 4);
+  pair(x + y, 5, 7);
+  pair(y - x, 6, 8);
 }
 
 // f^eq(rho, u_b) - f^eq(rho, u_f) (the non-equilibrium extrapolation shift
@@ -150,6 +187,17 @@ __device__ inline void wall_velocity(const StepParams& p, int c, int r, double& 
     side = 3;
   ub = p.uw[side][0];
   vb = p.uw[side][1];
+}
+
+template <typename Real>
+__device__ inline const StepParams::Coef<Real>& coef(const StepParams& p);
+template <>
+__device__ inline const StepParams::Coef<double>& coef<double>(const StepParams& p) {
+  return p.c64;
+}
+template <>
+__device__ inline const StepParams::Coef<float>& coef<float>(const StepParams& p) {
+  return p.c32;
 }
 
 template <typename Real>

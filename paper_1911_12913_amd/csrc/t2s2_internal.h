@@ -51,6 +51,17 @@ struct StepParams {
   double Fx, Fy;
   double uw[4][2];
   int has_force;
+  // The coefficients in the arithmetic type of the kernel: cPg, cQg, cRs,
+  // A, and per lattice-weight class c (rest, axis, diagonal) the products
+  // kP[c] = cPe w_c, kQ[c] = cQe w_c, kR[c] = cRe w_c, which multiply
+  // E = drho + rho X of f^eq - w = w E.
+  template <typename Real>
+  struct Coef {
+    Real cPg, cQg, cRs, A;
+    Real kP[3], kQ[3], kR[3];
+  };
+  Coef<double> c64;
+  Coef<float> c32;
 };
 
 struct AuxParams {

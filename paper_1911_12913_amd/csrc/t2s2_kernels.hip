@@ -60,25 +60,41 @@ __device__ inline void row_weights(const Real* table, int row, Real out[kWeights
 
 // Value of the neighbouring lane l-1 (from_below) or l+1 (from_above) of a
 // wave64, through DPP wave shifts (two 32-bit moves for a double).  Every
-// lane of the wave must hold a defined value; the edge lanes receive 0.
+// lane of the wave must hold a defined value.  bound_ctrl makes the edge
+// lane (no source lane) read 0, so the move does not depend on the old
+// destination value and needs no zero-fill before it.
+__device__ inline int dpp_shr1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ inline int dpp_shl1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
 __device__ inline double from_below(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
+  return __hiloint2double(dpp_shr1(__double2hiint(v)), dpp_shr1(__double2loint(v)));
 }
 __device__ inline double from_above(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
+  return __hiloint2double(dpp_shl1(__double2hiint(v)), dpp_shl1(__double2loint(v)));
 }
-__device__ inline float from_below(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+__device__ inline float from_below(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
+__device__ inline float from_above(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
+
+// Element at a 32-bit byte offset from a plane base: the row offset is
+// formed once per row in 32 bits and shared by the nine planes.  Every
+// population plane is under 4 GiB (checked when the context is created).
+template <typename T>
+__device__ inline const T* at_byte(const T* base, unsigned boff) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
 }
-__device__ inline float from_above(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+template <typename T>
+__device__ inline T* at_byte(T* base, unsigned boff) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
 }
 
-// sum_k w[k] v(lane + offset_k) for the 4 taps of the mixed difference
+// Row index brought into [0, n) by whole periods; the rows a piece touches
+// lie within a few rows of the grid, so this loops at most a few times.
+__device__ inline int wrap_near(int i, int n) {
+  while (i < 0) i += n;
+  while (i >= n) i -= n;
+  return i;
+}
+
+// acc + sum_k w[k] v(lane + offset_k) for the 4 taps of the mixed difference
 // along x: offsets (-2,-1,0,+1) for a positive velocity component (sx = 0),
 // (-1,0,+1,+2) for a negative one (sx = 1); the neighbours come from the
 // centre values of the other lanes.
@@ -99,6 +115,15 @@ __device__ inline Real x_taps(const Real* w, Real centre, Real acc) {
     acc += w[7] * p2;
   }
   return acc;
+}
+
+// Guo force term (eq 3.12) of direction q from E = (f^eq_q - w_q) / w_q:
+// F_q = 3 (F . (xi_q - u)) f^eq_q with f^eq_q = w_q (1 + E).
+template <typename Real>
+__device__ inline Real force_term(int q, const StepParams& p, Real ux, Real uy, Real E) {
+  const Real fu = static_cast<Real>(p.Fx) * (Real(ex_of(q)) - ux) +
+                  static_cast<Real>(p.Fy) * (Real(ey_of(q)) - uy);
+  return Real(3.0 * w_of(q)) * fu * (Real(1) + E);
 }
 
 // Resident waves per SIMD the register allocation must allow: the FP64 rings
@@ -181,9 +206,11 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
     const bool src_xl = !p.per_x && c == 1;
     const bool src_xr = !p.per_x && c == nx - 2;
 
-    Real qold[kQ], qnew[kQ];
+    // Q of the rows of the previous and of this iteration, alternating
+    // between two register arrays over the iteration pair.
+    Real qA[kQ], qB[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) qold[q] = qnew[q] = Real(0);
+    for (int q = 0; q < kQ; ++q) qA[q] = qB[q] = Real(0);
 
     // Iterations come in pairs (one per prefetch buffer); a trailing extra
     // iteration only reloads clamped rows and stores nothing (its rows fail
@@ -193,17 +220,20 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
     // Row loads run two iterations ahead in two register buffers, so two
     // iterations of loads are in flight while the stencil phases compute.
     Store gA[kQ], gB[kQ];
+    const int pitch = static_cast<int>(p.pitch);
     auto load_row = [&](int pr, Store (&gb)[kQ]) {
-      const int prm = p.per_y ? wrap(pr, ny) : clampi(pr, 0, ny - 1);
-      const long long base = static_cast<long long>(prm) * p.pitch + cm;
+      const int prm = p.per_y ? wrap_near(pr, ny) : clampi(pr, 0, ny - 1);
+      const unsigned boff =
+          (static_cast<unsigned>(prm) * static_cast<unsigned>(pitch) + static_cast<unsigned>(cm)) *
+          static_cast<unsigned>(sizeof(Store));
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) gb[q] = src[q * plane + base];
+      for (int q = 0; q < kQ; ++q) gb[q] = *at_byte(src + q * plane, boff);
     };
     load_row(y0 - kHalo + t, gA);
     load_row(y0 - kHalo + kRowsPerIter + t, gB);
     __syncthreads();  // ring zero-fill / previous piece complete
 
-    auto iteration = [&](const int it, Store (&gb)[kQ]) {
+    auto iteration = [&](const int it, Store (&gb)[kQ], Real (&qnew)[kQ], const Real (&qold)[kQ]) {
       const int p0 = y0 - kHalo + kRowsPerIter * it;
 
       // ---- phase 1: P (to LDS) and Q (registers) of row p0 + t.
@@ -217,24 +247,28 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
         load_row(pr + 2 * kRowsPerIter, gb);
         double s, jx, jy;
         moment_sums(g, s, jx, jy);
-        const double rho = 1.0 + s;
-        const double ir = recip(rho);
-        const double ux = jx * ir + p.half_dt * p.Fx;
-        const double uy = jy * ir + p.half_dt * p.Fy;
-        Real feq[kQ];
-        feq_dev(s, rho, ux, uy, feq);
-        Real F[kQ];
-        if (kForce) force_terms(p.Fx, p.Fy, ux, uy, feq, F);
-        const Real cPg = static_cast<Real>(p.cPg), cPe = static_cast<Real>(p.cPe);
-        const Real cQg = static_cast<Real>(p.cQg), cQe = static_cast<Real>(p.cQe);
+        Real rho, ux, uy;
+        velocity(s, jx, jy, rho, ux, uy);
+        if (kForce) {
+          ux += static_cast<Real>(p.half_dt * p.Fx);
+          uy += static_cast<Real>(p.half_dt * p.Fy);
+        }
+        const Real d = static_cast<Real>(s);
+        Real X[kQ];
+        eq_brackets(ux, uy, X);
+        const auto& k = coef<Real>(p);
         Real* slotP = ringP + (pr & (kRing - 1)) * kQ * kLanes;
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
-          Real Pq = cPg * g[q] + cPe * feq[q];
-          Real Qq = cQg * g[q] + cQe * feq[q];
+          // E = (f^eq_q - w_q) / w_q; P and Q take their f^eq coefficient
+          // times w_q per weight class.
+          const Real E = d + rho * X[q];
+          Real Pq = k.cPg * g[q] + k.kP[wclass(q)] * E;
+          Real Qq = k.cQg * g[q] + k.kQ[wclass(q)] * E;
           if (kForce) {
-            Pq += static_cast<Real>(p.cPF) * F[q];
-            Qq += static_cast<Real>(p.cQF) * F[q];
+            const Real Fq = force_term(q, p, ux, uy, E);
+            Pq += static_cast<Real>(p.cPF) * Fq;
+            Qq += static_cast<Real>(p.cQF) * Fq;
           }
           slotP[q * kLanes + lane] = Pq;
           qnew[q] = Qq;
@@ -250,7 +284,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
         const bool row_ok =
             r >= y0 - 2 && r < y1 + 2 && (p.per_y || (r >= 1 && r <= ny - 2));
         if (row_ok) {
-          const int rm = p.per_y ? wrap(r, ny) : r;
+          const int rm = p.per_y ? wrap_near(r, ny) : r;
           Real wyr[kWeightsPerNode];
           row_weights(weights_y<Real>(p), rm, wyr);
           // One base pointer per ring row r-2 .. r+2 at this lane.
@@ -258,7 +292,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
 #pragma unroll
           for (int o = 0; o < 5; ++o)
             rb[o] = ringP + ((r + o - 2) & (kRing - 1)) * kQ * kLanes + lane;
-          const Real A = static_cast<Real>(p.A);
+          const auto& k = coef<Real>(p);
           Real S[kQ];
 #pragma unroll
           for (int q = 0; q < kQ; ++q) {
@@ -269,27 +303,28 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
             if (ey_of(q) != 0) {
               const int sy = ey_of(q) > 0 ? 0 : 1;
 #pragma unroll
-              for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][q * kLanes];
+              for (int k2 = 0; k2 < kTaps; ++k2) acc += wyr[sy * kTaps + k2] * rb[k2 + sy][q * kLanes];
             }
-            S[q] = centre + A * acc;
+            S[q] = q == 0 ? centre : centre + k.A * acc;
           }
           double s, jx, jy;
           moment_sums(S, s, jx, jy);
-          const double rho = 1.0 + s;
-          const double ir = recip(rho);
-          const double ux = jx * ir + p.half_h * p.Fx;
-          const double uy = jy * ir + p.half_h * p.Fy;
-          Real feq[kQ];
-          feq_dev(s, rho, ux, uy, feq);
-          Real F[kQ];
-          if (kForce) force_terms(p.Fx, p.Fy, ux, uy, feq, F);
-          const Real cRs = static_cast<Real>(p.cRs), cRe = static_cast<Real>(p.cRe);
+          Real rho, ux, uy;
+          velocity(s, jx, jy, rho, ux, uy);
+          if (kForce) {
+            ux += static_cast<Real>(p.half_h * p.Fx);
+            uy += static_cast<Real>(p.half_h * p.Fy);
+          }
+          const Real d = static_cast<Real>(s);
+          Real X[kQ];
+          eq_brackets(ux, uy, X);
           Real R[kQ];
           R[0] = Real(0);
 #pragma unroll
           for (int q = 1; q < kQ; ++q) {
-            Real Rq = cRs * S[q] + cRe * feq[q];
-            if (kForce) Rq += static_cast<Real>(p.cRF) * F[q];
+            const Real E = d + rho * X[q];
+            Real Rq = k.cRs * S[q] + k.kR[wclass(q)] * E;
+            if (kForce) Rq += static_cast<Real>(p.cRF) * force_term(q, p, ux, uy, E);
             R[q] = Rq;
           }
           if (lane_r && col_interior) {
@@ -310,7 +345,8 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
                   double ub, vb;
                   wall_velocity(p, c + dx, r + dy, ub, vb);
                   Real sh[kQ];
-                  nee_shift(rho, ux, uy, ub, vb, sh);
+                  nee_shift(static_cast<double>(rho), static_cast<double>(ux),
+                            static_cast<double>(uy), ub, vb, sh);
                   Real* slotW = dy == 1 ? topR : ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
 #pragma unroll
                   for (int q = 1; q < kQ; ++q)
@@ -354,19 +390,20 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
             out[q] = acc;
           }
           if (lane_o && col_interior) {
-            const long long base = static_cast<long long>(o) * p.pitch + c;
+            const unsigned boff =
+                (static_cast<unsigned>(o) * static_cast<unsigned>(pitch) + static_cast<unsigned>(c)) *
+                static_cast<unsigned>(sizeof(Store));
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) store_state(dst + q * plane + base, Cvt<Store>::st(out[q]));
+            for (int q = 0; q < kQ; ++q)
+              store_state(at_byte(dst + q * plane, boff), Cvt<Store>::st(out[q]));
           }
         }
       }
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) qold[q] = qnew[q];
     };
 
     for (int it = 0; it < niter; it += 2) {
-      iteration(it, gA);
-      iteration(it + 1, gB);
+      iteration(it, gA, qA, qB);
+      iteration(it + 1, gB, qB, qA);
     }
     __syncthreads();  // the next piece reuses the rings
   }
