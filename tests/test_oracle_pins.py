@@ -462,3 +462,27 @@ def test_absolute_and_deviation_representations_agree():
     a = oracle.run(case, oracle.init(case, offset=0.0), 200, offset=0.0)
     b = oracle.run(case, oracle.init(case, offset=1.0), 200, offset=1.0)
     assert np.abs((a - WQ[:, None, None]) - b).max() < 1e-14
+
+
+@pytest.mark.parametrize("omega,stable", [(0.46, False), (4.6, True)])
+def test_tgv_cfl_09_stability_depends_on_dt_over_tau(omega, stable):
+    """T2S2-FDLBM1 at CFL 0.9, eta = 0.01 on a periodic uniform grid: with
+    dt / tau = 0.46 (the value a 4096^2 grid over [0, 2pi]^2 gets at
+    nu = 1e-3) seeded round-off-size noise grows without bound within a few
+    hundred steps; with dt / tau = 4.6 (nu = 1e-4 on 4096^2) the vortex
+    decays smoothly.  The stability region of the scheme depends on tau / dt
+    as well as on the CFL number (Sec. 4, von Neumann analysis); the
+    throughput workload therefore runs at nu = 1e-4, same grid and work."""
+    n = 64
+    dt = 0.9 * 2 * math.pi / n
+    nu = dt / omega * oracle.CS2
+    case = W.tgv_case(n, n, u0=0.01, nu=nu, cfl=0.9, eta=0.01)
+    phi = oracle.init(case) + W.random_state((9, n, n), 1e-9, 1)
+    with np.errstate(all="ignore"):
+        phi = oracle.run(case, phi, 400)
+        _, u, v = oracle.moments(case, phi)
+        umax = float(np.nanmax(np.abs(u))) if np.isfinite(u).any() else math.inf
+    if stable:
+        assert np.isfinite(phi).all() and umax < 0.01
+    else:
+        assert not np.isfinite(phi).all() or umax > 1.0
