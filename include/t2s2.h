@@ -111,6 +111,22 @@ int t2s2_init_distributions(t2s2_ctx* ctx, const double* g);
 /* Advance nsteps >= 0 time steps (Sec. 2D, eq 2.23); asynchronous. */
 int t2s2_step(t2s2_ctx* ctx, int64_t nsteps);
 
+/* Launch plumbing for short steps (small meshes are launch-bound): record
+ * steps_per_graph (even, >= 2) consecutive steps of t2s2_step -- the same
+ * kernels, the same Sec. 2D step -- into a HIP graph owned by the context,
+ * replacing any earlier one.  Needs a non-default bound stream
+ * (T2S2_ERR_UNSUPPORTED otherwise).  Nothing executes during the capture.
+ * Rebinding the context drops the graph.  The HIP runtime allocates the
+ * graph's own resources. */
+int t2s2_graph_capture(t2s2_ctx* ctx, int steps_per_graph);
+
+/* Advance nsteps >= 0 steps like t2s2_step, replaying the captured graph for
+ * whole multiples of its length and taking the rest (and, when the state
+ * sits in the other buffer than at capture, one step first) as plain
+ * launches.  Results are bitwise those of t2s2_step.  Asynchronous.
+ * T2S2_ERR_NOT_BOUND if no graph was captured. */
+int t2s2_graph_step(t2s2_ctx* ctx, int64_t nsteps);
+
 /* Index (0 = state_a, 1 = state_b) of the buffer holding the current state. */
 int t2s2_current(const t2s2_ctx* ctx);
 

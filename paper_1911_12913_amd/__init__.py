@@ -76,6 +76,8 @@ def load_library(path: str = LIB_PATH):
         "t2s2_init_macro": (i, [vp, vp, vp, vp, vp]),
         "t2s2_init_distributions": (i, [vp, vp]),
         "t2s2_step": (i, [vp, i64]),
+        "t2s2_graph_capture": (i, [vp, i]),
+        "t2s2_graph_step": (i, [vp, i64]),
         "t2s2_current": (i, [vp]),
         "t2s2_steps_taken": (i64, [vp]),
         "t2s2_dt": (d, [vp]),
@@ -104,7 +106,8 @@ def load_library(path: str = LIB_PATH):
 
 def exported_symbols() -> Sequence[str]:
     return ("t2s2_create", "t2s2_state_bytes", "t2s2_workspace_bytes", "t2s2_bind",
-            "t2s2_init_macro", "t2s2_init_distributions", "t2s2_step", "t2s2_current",
+            "t2s2_init_macro", "t2s2_init_distributions", "t2s2_step", "t2s2_graph_capture",
+            "t2s2_graph_step", "t2s2_current",
             "t2s2_steps_taken", "t2s2_dt", "t2s2_moments", "t2s2_read_distributions",
             "t2s2_diagnostics", "t2s2_omega", "t2s2_adjoint_state_bytes",
             "t2s2_adjoint_scratch_bytes", "t2s2_bind_adjoint", "t2s2_adjoint_seed_velocity",
@@ -222,6 +225,14 @@ class Context:
     def step(self, n: int = 1):
         _check(_lib.t2s2_step(self._h, int(n)))
 
+    def graph_capture(self, steps_per_graph: int):
+        """Record steps_per_graph (even) steps into a HIP graph; needs the
+        context to be bound to a non-default stream."""
+        _check(_lib.t2s2_graph_capture(self._h, int(steps_per_graph)))
+
+    def graph_step(self, n: int):
+        _check(_lib.t2s2_graph_step(self._h, int(n)))
+
     def moments(self):
         t = self._torch
         out = [t.empty((self.ny, self.nx), dtype=t.float64, device=self.device) for _ in range(3)]
@@ -308,12 +319,13 @@ class Context:
         return dict(zip(DIAG_NAMES, list(out)))
 
 
-def context_for_case(case, storage="f64", device=None, **overrides) -> Context:
+def context_for_case(case, storage="f64", device=None, stream=None, **overrides) -> Context:
     """Context for a workloads.Case-like object (x, y, periodic flags, nu,
-    cfl/dt, eta, A, force, u_wall)."""
+    cfl/dt, eta, A, force, u_wall), bound to `stream` (a torch stream;
+    default: the current stream)."""
     kw = dict(nu=case.nu, cfl=case.cfl, dt=case.dt or 0.0, eta=case.eta, A=case.A,
               force=case.force, u_wall=case.u_wall, periodic_x=case.periodic_x,
               periodic_y=case.periodic_y, period_x=case.period_x, period_y=case.period_y,
               storage=storage)
     kw.update(overrides)
-    return Context(make_config(**kw), case.x, case.y, device=device)
+    return Context(make_config(**kw), case.x, case.y, device=device, stream=stream)

@@ -142,7 +142,22 @@ struct t2s2_ctx {
   bool adj_bound = false;
   double* adj_partial = nullptr;
   size_t adj_state_bytes = 0;
+  // captured multi-step graph
+  hipGraphExec_t graph = nullptr;
+  int graph_steps = 0;
+  int graph_cur = 0;  // buffer holding the state when the graph starts
+  ~t2s2_ctx() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+  }
 };
+
+namespace {
+void drop_graph(t2s2_ctx* c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_steps = 0;
+}
+}  // namespace
 
 extern "C" {
 
@@ -312,6 +327,7 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   if ((reinterpret_cast<uintptr_t>(state_a) | reinterpret_cast<uintptr_t>(state_b) |
        reinterpret_cast<uintptr_t>(workspace)) & 255)
     return fail(T2S2_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+  drop_graph(c);  // a captured graph holds the previous buffer addresses
   c->state[0] = state_a;
   c->state[1] = state_b;
   c->ws = static_cast<char*>(workspace);
@@ -407,6 +423,67 @@ int t2s2_step(t2s2_ctx* c, int64_t nsteps) {
     ++c->steps;
   }
   return T2S2_OK;
+}
+
+int t2s2_graph_capture(t2s2_ctx* c, int steps_per_graph) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (steps_per_graph < 2 || (steps_per_graph & 1))
+    return fail(T2S2_ERR_INVALID_ARG, "steps_per_graph must be even and >= 2");
+  if (c->stream == nullptr)
+    return fail(T2S2_ERR_UNSUPPORTED, "graph capture needs a non-default stream");
+  drop_graph(c);
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(e, "graph capture: begin");
+  // Record the launches of steps_per_graph steps; nothing executes, so the
+  // host-side buffer index is advanced on a copy only.
+  int cur = c->cur;
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < steps_per_graph && le == hipSuccess; ++k) {
+    StepParams sp = c->sp;
+    sp.src = c->state[cur];
+    sp.dst = c->state[1 - cur];
+    le = launch_step(c->cfg.storage, sp, c->grid, c->stream);
+    cur = 1 - cur;
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->stream, &g);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(le != hipSuccess ? le : e, "graph capture: launches");
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "graph capture: instantiate");
+  c->graph = exec;
+  c->graph_steps = steps_per_graph;
+  c->graph_cur = c->cur;
+  return T2S2_OK;
+}
+
+int t2s2_graph_step(t2s2_ctx* c, int64_t nsteps) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (!c->graph) return fail(T2S2_ERR_NOT_BOUND, "no graph captured");
+  if (nsteps < 0) return fail(T2S2_ERR_INVALID_ARG, "nsteps < 0");
+  int64_t left = nsteps;
+  int rc = T2S2_OK;
+  // The graph reads the buffer that held the state at capture; an odd
+  // number of plain steps since then is evened out with one plain step.
+  if (left > 0 && c->cur != c->graph_cur) {
+    if ((rc = t2s2_step(c, 1)) != T2S2_OK) return rc;
+    --left;
+  }
+  while (left >= c->graph_steps) {
+    hipError_t e = hipGraphLaunch(c->graph, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    c->steps += c->graph_steps;  // an even count leaves c->cur unchanged
+    left -= c->graph_steps;
+  }
+  return left > 0 ? t2s2_step(c, left) : T2S2_OK;
 }
 
 int t2s2_current(const t2s2_ctx* c) { return c ? c->cur : -1; }

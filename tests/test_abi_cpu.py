@@ -97,6 +97,20 @@ def test_calls_on_unbound_context_fail_without_device():
     assert lib.t2s2_moments(h, None, None, None) == t2s2.ERR_NOT_BOUND
     assert lib.t2s2_bind(h, None, None, None, None) == t2s2.ERR_INVALID_ARG
     assert lib.t2s2_step(None, 1) == t2s2.ERR_INVALID_ARG
+    assert lib.t2s2_graph_capture(h, 2) == t2s2.ERR_NOT_BOUND
+    assert lib.t2s2_graph_step(h, 4) == t2s2.ERR_NOT_BOUND
+    assert lib.t2s2_graph_capture(None, 2) == t2s2.ERR_INVALID_ARG
+    lib.t2s2_destroy(h)
+
+
+def test_oversized_plane_is_unsupported():
+    """The step kernel addresses one population plane with 32-bit byte
+    offsets: a plane of 4 GiB or more is refused at create."""
+    lib = t2s2.load_library()
+    rc, h = _create(_good_cfg(), _axis(30000), _axis(30000))
+    assert rc == t2s2.ERR_UNSUPPORTED and not h.value
+    rc, h = _create(_good_cfg(storage=t2s2.STORAGE["f32"]), _axis(30000), _axis(30000))
+    assert rc == t2s2.OK
     lib.t2s2_destroy(h)
 
 

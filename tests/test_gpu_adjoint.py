@@ -184,3 +184,31 @@ def test_fp32_adjoint_against_fp64_adjoint():
     e_nu = abs(grads["f32"][2] - grads["f64"][2]) / abs(grads["f64"][2])
     print(f"    FP32 vs FP64 adjoint: dL/du0 rel L2 {e_u:.2e}, dL/dnu rel {e_nu:.2e}", flush=True)
     assert e_u < 1e-2 and e_nu < 1e-2
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_step_time_513(storage):
+    """Time of one adjoint step (which recomputes the forward step it
+    reverses) against one forward step, 513^2 cavity; reported."""
+    case = _cavity513()
+    ctx = t2s2.context_for_case(case, storage=storage)
+    ctx.enable_adjoint()
+    ctx.init_macro(np.ones((case.ny, case.nx)), *W.gaussian_velocity(case.nx, case.ny, 1e-3, 1))
+    state = ctx.save_state()
+    lam_a, lam_b = ctx.adjoint_buffer(), ctx.adjoint_buffer()
+    zeros = _dev(np.zeros((case.ny, case.nx)))
+    ctx.adjoint_seed_velocity(state, zeros, zeros, lam_a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for label, fn in (("forward step", lambda: ctx.step(1)),
+                      ("adjoint step", lambda: ctx.adjoint_step(state, lam_a, lam_b))):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(ctx.stream)
+        for _ in range(50):
+            fn()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 50 * 1e3
+        print(f"    513^2 {storage} {label}: {us:.1f} us "
+              f"({case.nx * case.ny / us:.0f} MLUPS)", flush=True)

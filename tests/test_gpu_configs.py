@@ -1,0 +1,207 @@
+"""GPU parity at the full sizes of the measured workloads, HIP-graph stepping,
+and the precision-form errors of the large cavity.
+
+* Taylor-Green 4096 x 4096 (the throughput workload of bench.py, in the
+  launch configuration bench.py times): two FP64 steps against the oracle on
+  the whole grid; the FP32 storage form's error at the same point.
+* Lid-driven cavity 257 x 257 (tanh mesh, Re 1000, CFL 0.9): 5000 steps
+  against the oracle; HIP-graph stepping bitwise equal to plain launches,
+  with eager work between replays; MLUPS with and without the graph.
+* Lid-driven cavity 2049 x 2049 (Re 5000, CFL 0.9, eta 0.05): 20 FP64 steps
+  against the oracle; after 20000 steps the relative L2 velocity error of
+  the FP32, FP16 and BF16 storage forms against FP64.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+t2s2 = pytest.importorskip("paper_1911_12913_amd")
+
+
+def _rel(a, b):
+    return W.rel_l2(np.asarray(a), np.asarray(b))
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _host_threads():
+    import os
+
+    return min(16, os.cpu_count() or 1)
+
+
+def _vel(ctx):
+    _, u, v = ctx.moments()
+    return torch.stack([u, v]).cpu().numpy()
+
+
+def test_tgv4096_bench_configuration_matches_oracle(monkeypatch):
+    """bench.py's workload and launch configuration (default block count):
+    TGV 4096^2, U0 0.01, nu 1e-4, CFL 0.9, eta 0.01, eq 3.5 initial state,
+    two steps; relative L2 <= 1e-12 on the state and on (u, v) against the
+    FP64 oracle over the whole grid, and the FP32 storage form within 1e-6."""
+    monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+    case = W.tgv_case(4096, 4096, u0=0.01, nu=1e-4, cfl=0.9, eta=0.01)
+    _say("[gpu] tgv4096: oracle init + 2 steps on the host")
+    t0 = time.time()
+    ref = oracle.run(case, oracle.init(case), 2, threads=_host_threads())
+    _, ur, vr = oracle.moments(case, ref)
+    vel_ref = np.stack([ur, vr])
+    _say(f"    oracle done in {time.time() - t0:.1f} s")
+    for storage, tol_g, tol_v in (("f64", 1e-12, 1e-12), ("f32", None, 1e-6)):
+        _say(f"[gpu] tgv4096 storage={storage}: init_macro + 2 steps")
+        ctx = t2s2.context_for_case(case, storage=storage)
+        ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
+        ctx.step(2)
+        vel = _vel(ctx)
+        ev = _rel(vel, vel_ref)
+        msg = f"    {storage}: (u,v) rel L2 {ev:.3e}"
+        if tol_g is not None:
+            g = ctx.read_distributions().cpu().numpy()
+            eg = _rel(g, ref)
+            msg += f"  state rel L2 {eg:.3e}"
+            del g
+            assert eg <= tol_g
+        _say(msg)
+        assert ev <= tol_v
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+
+
+def _cavity257():
+    return W.cavity_case(256, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
+
+
+def test_cavity257_5000_steps_matches_oracle():
+    """Cavity 257^2 (tanh mesh c = 1.5, Re 1000, CFL 0.9, eta 0.1, rest +
+    U(+-1e-6) noise, seed 0): 5000 FP64 steps, relative L2 <= 1e-12."""
+    case = _cavity257()
+    phi0 = oracle.init(case)
+    _say("[gpu] cavity257: oracle 5000 steps on the host")
+    ref = oracle.run(case, phi0, 5000, threads=_host_threads())
+    _say("[gpu] cavity257: 5000 GPU steps")
+    ctx = t2s2.context_for_case(case)
+    ctx.init_distributions(torch.from_numpy(phi0))
+    ctx.step(5000)
+    g = ctx.read_distributions().cpu().numpy()
+    vel = _vel(ctx)
+    _, ur, vr = oracle.moments(case, ref)
+    eg, ev = _rel(g, ref), _rel(vel, np.stack([ur, vr]))
+    _say(f"    state rel L2 {eg:.3e}  (u,v) rel L2 {ev:.3e}")
+    assert eg <= 1e-12 and ev <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["cavity65", "tgv48x40"])
+def test_graph_stepping_is_bitwise_plain_stepping(kind):
+    """A captured multi-step HIP graph gives bitwise the state of plain
+    launches, replay after replay, with plain steps and host synchronisation
+    between the replays (which also leave the state in the other buffer)."""
+    if kind == "cavity65":
+        case = W.cavity_case(64, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
+    else:
+        case = W.tgv_case(48, 40, u0=0.05, nu=0.01, cfl=0.6, eta=0.05)
+    phi0 = oracle.init(case)
+    _say(f"[gpu] graph stepping {kind}")
+    s_plain, s_graph = torch.cuda.Stream(), torch.cuda.Stream()
+    a = t2s2.context_for_case(case, stream=s_plain)
+    b = t2s2.context_for_case(case, stream=s_graph)
+    for c in (a, b):
+        c.init_distributions(torch.from_numpy(phi0))
+    b.graph_capture(10)
+    for rep, n in enumerate((30, 25, 40)):
+        a.step(n)
+        b.graph_step(n)
+        torch.cuda.synchronize()
+        ga, gb = a.read_distributions().cpu().numpy(), b.read_distributions().cpu().numpy()
+        assert np.array_equal(ga, gb), f"replay {rep}"
+        a.step(1)
+        b.step(1)
+        torch.cuda.synchronize()
+    assert a.steps_taken == b.steps_taken == 98
+
+
+def test_cavity257_graph_vs_plain_throughput():
+    """MLUPS of the 257^2 cavity (a launch-bound size) with plain launches
+    and with a captured 100-step graph; both must agree bitwise."""
+    case = _cavity257()
+    phi0 = oracle.init(case)
+    s = torch.cuda.Stream()
+    nodes = case.nx * case.ny
+    res = {}
+    states = {}
+    for mode in ("plain", "graph"):
+        ctx = t2s2.context_for_case(case, stream=s)
+        ctx.init_distributions(torch.from_numpy(phi0))
+        if mode == "graph":
+            ctx.graph_capture(100)
+        run = ctx.step if mode == "plain" else ctx.graph_step
+        run(200)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        run(5000)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[mode] = nodes * 5000 / (ms * 1e-3) / 1e6
+        states[mode] = ctx.read_distributions().cpu().numpy()
+        _say(f"    cavity257 {mode}: {ms / 5000 * 1e3:.2f} us/step, {res[mode]:.0f} MLUPS")
+    assert np.array_equal(states["plain"], states["graph"])
+
+
+def _cavity2049():
+    return W.cavity_case(2048, lid=0.1, re=5000.0, cfl=0.9, eta=0.05, noise=1e-6, seed=0)
+
+
+def test_cavity2049_fp64_matches_oracle():
+    """Cavity 2049^2 (Re 5000, CFL 0.9, eta 0.05): 20 FP64 steps against the
+    oracle on the whole grid, relative L2 <= 1e-12."""
+    case = _cavity2049()
+    phi0 = oracle.init(case)
+    _say("[gpu] cavity2049: oracle 20 steps on the host")
+    ref = oracle.run(case, phi0, 20, threads=_host_threads())
+    ctx = t2s2.context_for_case(case)
+    ctx.init_distributions(torch.from_numpy(phi0))
+    ctx.step(20)
+    g = ctx.read_distributions().cpu().numpy()
+    eg = _rel(g, ref)
+    _, ur, vr = oracle.moments(case, ref)
+    ev = _rel(_vel(ctx), np.stack([ur, vr]))
+    _say(f"    state rel L2 {eg:.3e}  (u,v) rel L2 {ev:.3e}")
+    assert eg <= 1e-12 and ev <= 1e-12
+
+
+def test_cavity2049_precision_forms_after_20000_steps():
+    """Precision form on the 2049^2 cavity, 20000 steps: relative L2 of the
+    velocity field of each storage form against the FP64 result (which
+    matches the oracle to round-off, see the test above).  Reported; the
+    bounds only catch a broken form."""
+    case = _cavity2049()
+    ux0, uy0, rho0 = case.ux0, case.uy0, case.rho0
+    vel = {}
+    for storage in ("f64", "f32", "f16", "bf16"):
+        _say(f"[gpu] cavity2049 storage={storage}: 20000 steps")
+        ctx = t2s2.context_for_case(case, storage=storage)
+        ctx.init_macro(rho0, ux0, uy0)
+        ctx.step(20000)
+        vel[storage] = _vel(ctx)
+        diag = ctx.diagnostics(raise_nonfinite=False)
+        _say(f"    max|u| {diag['max_speed']:.4e}  nonfinite {diag['nonfinite']}")
+        ctx.close()
+        del ctx
+    bounds = {"f32": 1e-3, "f16": 0.5, "bf16": 1.0}
+    for storage, bound in bounds.items():
+        e = _rel(vel[storage], vel["f64"])
+        _say(f"    {storage}: velocity rel L2 vs FP64 after 20000 steps {e:.3e}")
+        assert e <= bound
