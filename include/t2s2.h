@@ -53,6 +53,13 @@ extern "C" {
 #define T2S2_BF16_DEV 2
 #define T2S2_F16_DEV 3
 
+/* Time-marching scheme (Sec. 2A, Sec. 2D).  T2S2_FDLBM1: eq 2.23, the
+ * intermediate stage at t + A dt (A = 1/2: T2S2-FDLBM1, A = 0: T1S2).
+ * T2S2_FDLBM2: eq 5.23, f~^{n+1} = f~^{+,n} + dt/2 (L(f^n) + L(f^{n+1})) with
+ * f^{n+1} predicted by a full-step characteristic update; A is not used. */
+#define T2S2_FDLBM1 1
+#define T2S2_FDLBM2 2
+
 /* Number of values written by t2s2_diagnostics. */
 #define T2S2_NDIAG 6
 
@@ -70,6 +77,7 @@ typedef struct t2s2_config {
   double period_x;
   double period_y;
   int storage;          /* T2S2_F64, T2S2_F32_DEV, T2S2_BF16_DEV, T2S2_F16_DEV */
+  int scheme;           /* T2S2_FDLBM1 (0 is read as this) or T2S2_FDLBM2 */
 } t2s2_config;
 
 typedef struct t2s2_ctx t2s2_ctx;
@@ -171,7 +179,8 @@ size_t t2s2_adjoint_state_bytes(const t2s2_ctx* ctx);
 size_t t2s2_adjoint_scratch_bytes(const t2s2_ctx* ctx);
 
 /* Attach the adjoint scratch (device, 256-byte aligned).  Returns
- * T2S2_ERR_UNSUPPORTED for forced flows.  No device call. */
+ * T2S2_ERR_UNSUPPORTED for forced flows and for T2S2_FDLBM2.  No device
+ * call. */
 int t2s2_bind_adjoint(t2s2_ctx* ctx, void* scratch);
 
 /* lambda = d(<gu, u> + <gv, v>)/dg of the velocity of eq 3.3 at every node,

@@ -46,6 +46,7 @@ class Config(ctypes.Structure):
         ("period_x", ctypes.c_double),
         ("period_y", ctypes.c_double),
         ("storage", ctypes.c_int),
+        ("scheme", ctypes.c_int),
     ]
 
 
@@ -124,7 +125,9 @@ def _check(rc: int):
 def make_config(*, nu: float, cfl: float = 0.0, dt: float = 0.0, eta: float = 0.01,
                 A: float = 0.5, force=(0.0, 0.0), u_wall=None, periodic_x: bool = True,
                 periodic_y: bool = True, period_x: float = 0.0, period_y: float = 0.0,
-                storage="f64") -> Config:
+                storage="f64", scheme: int = 1) -> Config:
+    """scheme 1: T2S2-FDLBM1 family (A = 1/2 FDLBM1, A = 0 T1S2); scheme 2:
+    T2S2-FDLBM2."""
     cfg = Config()
     cfg.nu = float(nu)
     cfg.cfl = float(cfl)
@@ -141,6 +144,7 @@ def make_config(*, nu: float, cfl: float = 0.0, dt: float = 0.0, eta: float = 0.
     cfg.period_x = float(period_x)
     cfg.period_y = float(period_y)
     cfg.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    cfg.scheme = int(scheme)
     return cfg
 
 

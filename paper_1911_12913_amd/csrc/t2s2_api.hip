@@ -185,6 +185,8 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   if (!(cfg->A >= 0.0 && cfg->A <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "A not in [0,1]");
   if (cfg->storage < T2S2_F64 || cfg->storage > T2S2_F16_DEV)
     return fail(T2S2_ERR_INVALID_ARG, "unknown storage");
+  if (cfg->scheme != 0 && cfg->scheme != T2S2_FDLBM1 && cfg->scheme != T2S2_FDLBM2)
+    return fail(T2S2_ERR_INVALID_ARG, "unknown scheme");
   // The step kernel addresses a population plane with 32-bit byte offsets.
   if (static_cast<long long>(ny) * ((nx + 63) / 64 * 64) *
           static_cast<long long>(storage_bytes(cfg->storage)) >= (1LL << 32))
@@ -212,8 +214,14 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   c->tau = 3.0 * cfg->nu;
   c->omega = std::isinf(cfg->nu) ? 0.0 : c->dt / c->tau;
 
-  const double A = cfg->A, w = c->omega, dt = c->dt;
+  const int scheme = cfg->scheme == T2S2_FDLBM2 ? 2 : 1;
+  c->cfg.scheme = scheme;
+  // T2S2-FDLBM2 predicts with a full step (h = dt, A = 1 in the maps below)
+  // and needs the physical f^n, which is P at A = 0.
+  const double A = scheme == 2 ? 1.0 : cfg->A, Ap = scheme == 2 ? 0.0 : A;
+  const double w = c->omega, dt = c->dt;
   StepParams& p = c->sp;
+  p.scheme = scheme;
   p.nx = nx;
   p.ny = ny;
   p.pitch = c->pitch;
@@ -225,9 +233,9 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   //   P = fbar^{+,h} = [(2 - A w) f~ + (1 + A) w f^eq + (1 + A) dt F] / (2 + w)
   //   Q = f~^+       = [(2 - w) f~ + 2 w f^eq + 2 dt F] / (2 + w)
   //   R = f(t*)      = [2 S + A w f^eq* + A dt F*] / (2 + A w)
-  p.cPg = (2.0 - A * w) / (2.0 + w);
-  p.cPe = (1.0 + A) * w / (2.0 + w);
-  p.cPF = (1.0 + A) * dt / (2.0 + w);
+  p.cPg = (2.0 - Ap * w) / (2.0 + w);
+  p.cPe = (1.0 + Ap) * w / (2.0 + w);
+  p.cPF = (1.0 + Ap) * dt / (2.0 + w);
   p.cQg = (2.0 - w) / (2.0 + w);
   p.cQe = 2.0 * w / (2.0 + w);
   p.cQF = 2.0 * dt / (2.0 + w);
@@ -356,18 +364,22 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   c->ap.jx = reinterpret_cast<const double*>(c->ws + c->off_jx);
   c->ap.jy = reinterpret_cast<const double*>(c->ws + c->off_jy);
   // One block per resident slot (CUs x blocks per CU), so every block runs
-  // in a single wave of the grid with an equal share of the strip-rows;
-  // fewer on small meshes (at least 16 strip-rows per block).  A multiple of
-  // 8 for the XCD-aware block order.
+  // in a single wave of the grid with an equal share of the strip-rows, as
+  // long as a share keeps at least 8 strip-rows.  Smaller meshes, where a
+  // block's march is a few latency-bound iterations, use one block per CU
+  // (equal work on every CU) while a share keeps at least 4 strip-rows, and
+  // below that one block per 4 strip-rows.  A multiple of 8 for the
+  // XCD-aware block order.
   int dev = 0, cus = 0;
   e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e, "bind: device query");
   const bool walls = !c->sp.per_x || !c->sp.per_y;
-  int per_cu = step_blocks_per_cu(c->cfg.storage, c->sp.has_force != 0, walls);
+  int per_cu = step_blocks_per_cu(c->cfg.storage, c->sp.has_force != 0, walls, c->sp.scheme);
   if (per_cu < 1) return fail(T2S2_ERR_HIP, "bind: step kernel cannot be resident");
   const long long rows = static_cast<long long>(c->sp.nstrips) * c->ny;
-  long long nb = std::min<long long>(static_cast<long long>(cus) * per_cu, rows / 16);
+  const long long slots = static_cast<long long>(cus) * per_cu;
+  long long nb = rows >= 8 * slots ? slots : (rows >= 4LL * cus ? cus : rows / 4);
   if (const char* env = std::getenv("T2S2_BLOCKS")) nb = std::atoll(env);
   nb = std::max<long long>(8, nb / 8 * 8);
   nb = std::min<long long>(nb, std::max<long long>(8, rows / 8 * 8));
@@ -549,6 +561,7 @@ int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
   if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
   if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
   if (c->sp.has_force) return fail(T2S2_ERR_UNSUPPORTED, "the adjoint covers unforced flows");
+  if (c->sp.scheme != 1) return fail(T2S2_ERR_UNSUPPORTED, "the adjoint covers T2S2-FDLBM1 / T1S2");
   if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255))
     return fail(T2S2_ERR_INVALID_ARG, "scratch must be a 256-byte aligned device pointer");
   AdjParams& a = c->adj;

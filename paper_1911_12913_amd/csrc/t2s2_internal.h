@@ -39,6 +39,7 @@ struct StepParams {
   int nstrips;  // strips of kStripOut output columns
   int nblocks;  // equal ranges of the nstrips * ny strip-rows, one per block
   int band;     // rows per band of the band-major strip-row order
+  int scheme;   // 1: T2S2-FDLBM1 family (eq 2.23); 2: T2S2-FDLBM2 (eq 5.23)
   const double* wx;   // [nx][2][4] dt-scaled x weights (FP64)
   const double* wy;   // [ny][2][4]
   const float* wx32;  // same in FP32
@@ -101,7 +102,7 @@ constexpr int kDiagSlots = 8;
 // Launchers (t2s2_kernels.hip).  Return hipError_t of the launch.
 hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s);
 // Resident step-kernel blocks per CU for this variant (-1 on error).
-int step_blocks_per_cu(int storage, bool force, bool walls);
+int step_blocks_per_cu(int storage, bool force, bool walls, int scheme);
 hipError_t launch_init_macro(int storage, const AuxParams& a, void* state, const double* rho,
                              const double* ux, const double* uy, const double* grad,
                              hipStream_t s);

@@ -130,16 +130,32 @@ __device__ inline Real force_term(int q, const StepParams& p, Real ux, Real uy, 
 // (68 KB per block) admit two blocks per CU; the FP32 rings admit four, which
 // the plain periodic FP32 / FP16 variants reach without spilling (the wall
 // and force variants, and BF16 with its conversions, settle for three).
-template <typename Store, bool kForce, bool kWalls>
-constexpr int kMinWaves = sizeof(typename Cvt<Store>::R) == 8
-                              ? 2
-                              : ((kForce || kWalls || std::is_same<Store, Bf16>::value) ? 3 : 4);
+// T2S2-FDLBM2's wider first ring (106 KB in FP64, 53 KB in FP32) admits one
+// and three blocks per CU.
+template <typename Store, bool kForce, bool kWalls, int kScheme>
+constexpr int kMinWaves =
+    sizeof(typename Cvt<Store>::R) == 8
+        ? (kScheme == 2 ? 1 : 2)
+        : ((kScheme == 2 || kForce || kWalls || std::is_same<Store, Bf16>::value) ? 3 : 4);
 
-template <typename Store, bool kForce, bool kWalls>
-__global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) void step_kernel(
+// Planes of the first LDS ring: P for T2S2-FDLBM1 (and T1S2); for
+// T2S2-FDLBM2, Q = f~^+ (the field the prediction advects) and, for the
+// eight moving directions, the physical f^n.
+template <int kScheme>
+constexpr int kPPlanes = kScheme == 2 ? 2 * kQ - 1 : kQ;
+
+// The fused step, templated on the storage type, the presence of a body
+// force, of walls, and on the scheme:
+//   kScheme 1: T2S2-FDLBM1 family (eq 2.23; A = 0 is T1S2);
+//   kScheme 2: T2S2-FDLBM2 (eq 5.23): f~^{n+1} = Q + dt/2 (L(f^n) + L(f^{n+1}))
+//     with f^{n+1} predicted by S = Q + dt L(Q) and unshifted with h = dt;
+//     L is linear, so the two gradients are taken as one, of T = f^n + R.
+template <typename Store, bool kForce, bool kWalls, int kScheme>
+__global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls, kScheme>)) void step_kernel(
     StepParams p) {
   using Real = typename Cvt<Store>::R;
-  __shared__ Real ringP[kRing * kQ * kLanes];       // [slot][q][lane]
+  constexpr int kNP = kPPlanes<kScheme>;
+  __shared__ Real ringP[kRing * kNP * kLanes];      // [slot][plane][lane]
   __shared__ Real ringR[kRing * (kQ - 1) * kLanes];  // [slot][q-1][lane]
   // R of the top wall row ny-1, kept out of the ring: it is written (eq 3.10)
   // by the wave that computes row ny-2, in the same phase in which the ring
@@ -153,7 +169,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
   Store* __restrict__ dst = static_cast<Store*>(p.dst);
   const long long plane = p.plane;
 
-  for (int i = threadIdx.x; i < kRing * kQ * kLanes; i += kBlockThreads) ringP[i] = Real(0);
+  for (int i = threadIdx.x; i < kRing * kNP * kLanes; i += kBlockThreads) ringP[i] = Real(0);
   for (int i = threadIdx.x; i < kRing * (kQ - 1) * kLanes; i += kBlockThreads) ringR[i] = Real(0);
   if (kWalls)
     for (int i = threadIdx.x; i < (kQ - 1) * kLanes; i += kBlockThreads) topR[i] = Real(0);
@@ -236,7 +252,8 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
     auto iteration = [&](const int it, Store (&gb)[kQ], Real (&qnew)[kQ], const Real (&qold)[kQ]) {
       const int p0 = y0 - kHalo + kRowsPerIter * it;
 
-      // ---- phase 1: P (to LDS) and Q (registers) of row p0 + t.
+      // ---- phase 1: P (to LDS) and Q (registers) of row p0 + t; for
+      // T2S2-FDLBM2 Q and f^n to LDS (P's coefficients then give f^n).
       {
         const int pr = p0 + t;
         Real g[kQ];
@@ -257,7 +274,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
         Real X[kQ];
         eq_brackets(ux, uy, X);
         const auto& k = coef<Real>(p);
-        Real* slotP = ringP + (pr & (kRing - 1)) * kQ * kLanes;
+        Real* slotP = ringP + (pr & (kRing - 1)) * kNP * kLanes;
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
           // E = (f^eq_q - w_q) / w_q; P and Q take their f^eq coefficient
@@ -270,7 +287,8 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
             Pq += static_cast<Real>(p.cPF) * Fq;
             Qq += static_cast<Real>(p.cQF) * Fq;
           }
-          slotP[q * kLanes + lane] = Pq;
+          slotP[q * kLanes + lane] = kScheme == 2 ? Qq : Pq;
+          if (kScheme == 2 && q > 0) slotP[(kQ + q - 1) * kLanes + lane] = Pq;
           qnew[q] = Qq;
         }
       }
@@ -291,7 +309,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
           const Real* rb[5];
 #pragma unroll
           for (int o = 0; o < 5; ++o)
-            rb[o] = ringP + ((r + o - 2) & (kRing - 1)) * kQ * kLanes + lane;
+            rb[o] = ringP + ((r + o - 2) & (kRing - 1)) * kNP * kLanes + lane;
           const auto& k = coef<Real>(p);
           Real S[kQ];
 #pragma unroll
@@ -327,10 +345,17 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
             if (kForce) Rq += static_cast<Real>(p.cRF) * force_term(q, p, ux, uy, E);
             R[q] = Rq;
           }
+          // T2S2-FDLBM2 stores T = f^n + R: the full step takes the
+          // gradient of both at once.
+          auto with_fn = [&](int q, int row, int ln, Real v) {
+            if (kScheme == 2)
+              v += ringP[(row & (kRing - 1)) * kNP * kLanes + (kQ + q - 1) * kLanes + ln];
+            return v;
+          };
           if (lane_r && col_interior) {
             Real* slotR = ringR + (r & (kRing - 1)) * (kQ - 1) * kLanes;
 #pragma unroll
-            for (int q = 1; q < kQ; ++q) slotR[(q - 1) * kLanes + lane] = R[q];
+            for (int q = 1; q < kQ; ++q) slotR[(q - 1) * kLanes + lane] = with_fn(q, r, lane, R[q]);
             // Wall nodes whose nearest interior node is this one (eq 3.10
             // on f(t*); corners take the diagonal neighbour).  Physical f
             // carries no force shift: u_f = sum xi R / rho = u*.
@@ -350,7 +375,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
                   Real* slotW = dy == 1 ? topR : ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
 #pragma unroll
                   for (int q = 1; q < kQ; ++q)
-                    slotW[(q - 1) * kLanes + lane + dx] = R[q] + sh[q];
+                    slotW[(q - 1) * kLanes + lane + dx] = with_fn(q, r + dy, lane + dx, R[q] + sh[q]);
                 }
               }
             }
@@ -379,7 +404,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
           for (int q = 1; q < kQ; ++q) {
             const int pq = (q - 1) * kLanes;
             const Real centre = rb[2][pq];
-            Real acc = qold[q];
+            Real acc = kScheme == 2 ? Real(0) : qold[q];
             if (ex_of(q) > 0) acc = x_taps<0>(wxr, centre, acc);
             if (ex_of(q) < 0) acc = x_taps<1>(wxr, centre, acc);
             if (ey_of(q) != 0) {
@@ -387,7 +412,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls>)) 
 #pragma unroll
               for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][pq];
             }
-            out[q] = acc;
+            out[q] = kScheme == 2 ? qold[q] + Real(0.5) * acc : acc;
           }
           if (lane_o && col_interior) {
             const unsigned boff =
@@ -606,21 +631,29 @@ __global__ __launch_bounds__(64) void diag_final_kernel(const double* partials, 
   }
 }
 
+template <typename Store, int kScheme>
+void launch_fused(const StepParams& p, dim3 g, dim3 b, hipStream_t s, bool walls) {
+  if (p.has_force) {
+    if (walls)
+      hipLaunchKernelGGL((step_kernel<Store, true, true, kScheme>), g, b, 0, s, p);
+    else
+      hipLaunchKernelGGL((step_kernel<Store, true, false, kScheme>), g, b, 0, s, p);
+  } else {
+    if (walls)
+      hipLaunchKernelGGL((step_kernel<Store, false, true, kScheme>), g, b, 0, s, p);
+    else
+      hipLaunchKernelGGL((step_kernel<Store, false, false, kScheme>), g, b, 0, s, p);
+  }
+}
+
 template <typename Store>
 hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
   const dim3 g(grid), b(kBlockThreads);
   const bool walls = !p.per_x || !p.per_y;
-  if (p.has_force) {
-    if (walls)
-      hipLaunchKernelGGL((step_kernel<Store, true, true>), g, b, 0, s, p);
-    else
-      hipLaunchKernelGGL((step_kernel<Store, true, false>), g, b, 0, s, p);
-  } else {
-    if (walls)
-      hipLaunchKernelGGL((step_kernel<Store, false, true>), g, b, 0, s, p);
-    else
-      hipLaunchKernelGGL((step_kernel<Store, false, false>), g, b, 0, s, p);
-  }
+  if (p.scheme == 2)
+    launch_fused<Store, 2>(p, g, b, s, walls);
+  else
+    launch_fused<Store, 1>(p, g, b, s, walls);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !walls) return e;
   const int perim = 2 * (p.nx + p.ny);
@@ -656,29 +689,34 @@ size_t storage_bytes(int storage) {
     default: return hipErrorInvalidValue;                             \
   }
 
-template <typename Store>
-int occupancy_t(bool force, bool walls) {
+template <typename Store, int kScheme>
+int occupancy_s(bool force, bool walls) {
   int n = 0;
   hipError_t e;
   if (force)
-    e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<Store, true, true>,
-                                                             kBlockThreads, 0)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<Store, true, false>,
-                                                             kBlockThreads, 0);
+    e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, step_kernel<Store, true, true, kScheme>, kBlockThreads, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, step_kernel<Store, true, false, kScheme>, kBlockThreads, 0);
   else
-    e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<Store, false, true>,
-                                                             kBlockThreads, 0)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<Store, false, false>,
-                                                             kBlockThreads, 0);
+    e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, step_kernel<Store, false, true, kScheme>, kBlockThreads, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, step_kernel<Store, false, false, kScheme>, kBlockThreads, 0);
   return e == hipSuccess ? n : -1;
 }
 
-int step_blocks_per_cu(int storage, bool force, bool walls) {
+template <typename Store>
+int occupancy_t(bool force, bool walls, int scheme) {
+  return scheme == 2 ? occupancy_s<Store, 2>(force, walls) : occupancy_s<Store, 1>(force, walls);
+}
+
+int step_blocks_per_cu(int storage, bool force, bool walls, int scheme) {
   switch (storage) {
-    case kF64: return occupancy_t<double>(force, walls);
-    case kF32: return occupancy_t<float>(force, walls);
-    case kBF16: return occupancy_t<Bf16>(force, walls);
-    case kF16: return occupancy_t<_Float16>(force, walls);
+    case kF64: return occupancy_t<double>(force, walls, scheme);
+    case kF32: return occupancy_t<float>(force, walls, scheme);
+    case kBF16: return occupancy_t<Bf16>(force, walls, scheme);
+    case kF16: return occupancy_t<_Float16>(force, walls, scheme);
     default: return -1;
   }
 }

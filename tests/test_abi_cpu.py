@@ -30,8 +30,18 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_config_struct_layout():
-    # 5 doubles, force[2], u_wall[4][2], 2 ints, 2 doubles, 1 int (+ padding)
+    # 5 doubles, force[2], u_wall[4][2], 2 ints, 2 doubles, 2 ints
     assert ctypes.sizeof(t2s2.Config) == 8 * 5 + 16 + 64 + 8 + 16 + 8
+    assert t2s2.Config.scheme.offset == 8 * 5 + 16 + 64 + 8 + 16 + 4
+
+
+def test_scheme_validation():
+    lib = t2s2.load_library()
+    for scheme, ok in ((0, True), (1, True), (2, True), (3, False), (-1, False)):
+        rc, h = _create(_good_cfg(scheme=scheme), _axis(20), _axis(20))
+        assert (rc == t2s2.OK) == ok, scheme
+        if h.value:
+            lib.t2s2_destroy(h)
 
 
 def _create(cfg, x, y):

@@ -219,3 +219,60 @@ def test_reduced_precision_error_vs_oracle(storage, tol):
     err = max(_rel(u, ur), _rel(v, vr))
     print(f"    {storage}: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
     assert err <= tol
+
+
+# ------------------------------------------------------ T2S2-FDLBM2 (eq 5.23)
+
+def _ragged_cavity(cfl):
+    case = W.cavity_case(64, lid=0.1, re=400.0, cfl=cfl, eta=0.1, noise=1e-6, seed=3)
+    case.x = W.tanh_walled(129, 1.5)
+    case.rho0 = np.ones((case.ny, 130))
+    rng = np.random.Generator(np.random.PCG64(4))
+    case.ux0 = np.zeros((case.ny, 130))
+    case.uy0 = np.zeros((case.ny, 130))
+    case.ux0[1:-1, 1:-1] = rng.uniform(-1e-6, 1e-6, (case.ny - 2, 128))
+    return case
+
+
+def test_fdlbm2_periodic_matches_oracle():
+    """T2S2-FDLBM2 on the periodic 150x70 Taylor-Green (k1 = 2, k2 = 1) with
+    seeded noise, CFL 0.5, 120 steps."""
+    case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.5, eta=0.05)
+    phi0 = oracle.init(case) + W.random_state((9, 70, 150), 1e-5, 8)
+    ref = oracle.run(case, phi0, 120, scheme=2)
+    _, g, d, u, v = _gpu_run(case, phi0, 120, scheme=2)
+    _compare(case, g, d, u, v, ref)
+
+
+@pytest.mark.parametrize("blocks", ["8", "16", "40"])
+def test_fdlbm2_walled_cavity_matches_oracle(blocks, monkeypatch):
+    """T2S2-FDLBM2 on the ragged 130x65 cavity (walls on all sides, moving
+    lid), CFL 0.5, 150 steps, cut into 8 to 40 block ranges."""
+    monkeypatch.setenv("T2S2_BLOCKS", blocks)
+    case = _ragged_cavity(0.5)
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 150, scheme=2)
+    _, g, d, u, v = _gpu_run(case, phi0, 150, scheme=2)
+    _compare(case, g, d, u, v, ref)
+
+
+def test_fdlbm2_forced_channel_matches_oracle():
+    """T2S2-FDLBM2 on the force-driven channel (x periodic, y walls), 400 steps."""
+    case = W.poiseuille_case(dt_over_y1=0.5, eta=0.1)
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 400, scheme=2)
+    _, g, d, u, v = _gpu_run(case, phi0, 400, scheme=2)
+    _compare(case, g, d, u, v, ref)
+
+
+def test_fdlbm2_fp32_error_vs_oracle():
+    """T2S2-FDLBM2 with FP32 deviation storage: velocity error against the
+    FP64 oracle, reported and bounded."""
+    case = W.tgv_case(64, 64, u0=0.01, nu=0.01, cfl=0.5, eta=0.01)
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 400, scheme=2)
+    _, g, d, u, v = _gpu_run(case, phi0, 400, storage="f32", scheme=2)
+    _, ur, vr = oracle.moments(case, ref)
+    err = _rel(np.stack([u, v]), np.stack([ur, vr]))
+    print(f"    f32 FDLBM2: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
+    assert err <= 3e-5

@@ -486,3 +486,33 @@ def test_tgv_cfl_09_stability_depends_on_dt_over_tau(omega, stable):
         assert np.isfinite(phi).all() and umax < 0.01
     else:
         assert not np.isfinite(phi).all() or umax > 1.0
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_table_2_fdlbm2_row(idx):
+    """Table 2, T2S2-FDLBM2 row (the eq 5.23 march; scheme 2 of the oracle):
+    E(u) at t_c with dt = pi/640 on 16x64 and 32x128."""
+    g = _gold("tgv_tables.json")["table2_fdlbm2_dt_pi_over_640_at_tc"]
+    nx, ny = g["grids"][idx]
+    case = _paper_tgv(nx, ny, dt=math.pi / 640)
+    n = int(math.floor(_tc() / case.dt))
+    phi = oracle.run(case, oracle.init(case), n, scheme=2, threads=8)
+    eu, _ = _tgv_errors(case, phi, n, case.dt)
+    assert eu == pytest.approx(g["Eu"][idx], rel=0.05)
+
+
+def test_fdlbm2_differs_from_fdlbm1_and_reduces_with_dt():
+    """The eq 5.23 march is a different scheme from eq 2.23 (their states
+    differ after a few steps) and, like it, converges as dt shrinks."""
+    case = W.tgv_case(24, 24, u0=0.05, nu=0.01, cfl=0.5, eta=0.05)
+    phi0 = oracle.init(case)
+    a = oracle.run(case, phi0, 50, scheme=1)
+    b = oracle.run(case, phi0, 50, scheme=2)
+    assert W.rel_l2(a, b) > 1e-6
+    T = 50 * oracle.time_step(case)
+    outs = []
+    for k in (1, 2, 4):
+        c = W.tgv_case(24, 24, u0=0.05, nu=0.01, cfl=0.5 / k, eta=0.05)
+        outs.append(oracle.run(c, phi0, 50 * k, scheme=2, dt=T / (50 * k)))
+    d1, d2 = W.rel_l2(outs[0], outs[1]), W.rel_l2(outs[1], outs[2])
+    assert d2 < 0.6 * d1
