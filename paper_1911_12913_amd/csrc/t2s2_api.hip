@@ -283,6 +283,8 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   // Launch plan: strips of kStripOut output columns; the block count is set
   // at bind time from the device's CU count and the kernel's occupancy.
   p.nstrips = (nx + kStripOut - 1) / kStripOut;
+  const int spb = strips_per_block(cfg->storage, scheme);
+  p.nunits = (p.nstrips + spb - 1) / spb;
   p.nblocks = 8;
   p.band = ny;
   c->grid = 8;
@@ -364,12 +366,12 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   c->ap.jx = reinterpret_cast<const double*>(c->ws + c->off_jx);
   c->ap.jy = reinterpret_cast<const double*>(c->ws + c->off_jy);
   // One block per resident slot (CUs x blocks per CU), so every block runs
-  // in a single wave of the grid with an equal share of the strip-rows, as
-  // long as a share keeps at least 8 strip-rows.  Smaller meshes, where a
-  // block's march is a few latency-bound iterations, use one block per CU
-  // (equal work on every CU) while a share keeps at least 4 strip-rows, and
-  // below that one block per 4 strip-rows.  A multiple of 8 for the
-  // XCD-aware block order.
+  // in a single wave of the grid with an equal share of the unit-rows (a
+  // unit is the block's group of neighbouring strips), as long as a share
+  // keeps at least 8 unit-rows.  Smaller meshes, where a block's march is a
+  // few latency-bound iterations, use one block per CU (equal work on every
+  // CU) while a share keeps at least 4 unit-rows, and below that one block
+  // per 4 unit-rows.  A multiple of 8 for the XCD-aware block order.
   int dev = 0, cus = 0;
   e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -377,7 +379,7 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   const bool walls = !c->sp.per_x || !c->sp.per_y;
   int per_cu = step_blocks_per_cu(c->cfg.storage, c->sp.has_force != 0, walls, c->sp.scheme);
   if (per_cu < 1) return fail(T2S2_ERR_HIP, "bind: step kernel cannot be resident");
-  const long long rows = static_cast<long long>(c->sp.nstrips) * c->ny;
+  const long long rows = static_cast<long long>(c->sp.nunits) * c->ny;
   const long long slots = static_cast<long long>(cus) * per_cu;
   long long nb = rows >= 8 * slots ? slots : (rows >= 4LL * cus ? cus : rows / 4);
   if (const char* env = std::getenv("T2S2_BLOCKS")) nb = std::atoll(env);
@@ -385,8 +387,8 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   nb = std::min<long long>(nb, std::max<long long>(8, rows / 8 * 8));
   c->sp.nblocks = static_cast<int>(nb);
   // Band height = one block's share, so that (away from the last band) each
-  // block owns exactly one strip of one band and the blocks of neighbouring
-  // strips march the same rows at the same time.
+  // block owns exactly one unit of one band and the blocks of neighbouring
+  // units march the same rows at the same time.
   c->sp.band = static_cast<int>(std::min<long long>(c->ny, std::max<long long>(1, (rows + nb - 1) / nb)));
   c->grid = static_cast<int>(nb);
   c->bound = true;

@@ -59,6 +59,13 @@ struct Cvt<_Float16> {
   __device__ static _Float16 st(float v) { return static_cast<_Float16>(v); }  // RNE
 };
 
+// Storage code of a storage type.
+template <typename S>
+constexpr int kStorageOf = std::is_same<S, double>::value  ? kF64
+                           : std::is_same<S, float>::value ? kF32
+                           : std::is_same<S, Bf16>::value  ? kBF16
+                                                           : kF16;
+
 __device__ inline int wrap(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;

@@ -29,6 +29,19 @@ constexpr int kWeightsPerNode = 2 * kTaps;
 // Storage codes (match include/t2s2.h).
 enum Storage { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3 };
 
+// Strips marched side by side by one block of the fused step.  Two for the
+// FP32-storage T2S2-FDLBM1 family: the cache lines the two strips share
+// are then loaded by one CU in the same iteration, and two such blocks
+// still fit on a CU.  One otherwise: FP64 rings fit only once per CU in a
+// two-strip block, and a single block per CU stalls the whole CU at every
+// barrier; T2S2-FDLBM2's wider rings do not fit twice.
+__host__ __device__ constexpr int strips_per_block(int storage, int scheme) {
+  return (scheme == 1 && storage == kF32) ? 2 : 1;
+}
+__host__ __device__ constexpr int step_threads(int storage, int scheme) {
+  return kBlockThreads * strips_per_block(storage, scheme);
+}
+
 struct StepParams {
   const void* src;
   void* dst;
@@ -37,7 +50,8 @@ struct StepParams {
   long long plane;  // elements per population plane (ny * pitch)
   int per_x, per_y;
   int nstrips;  // strips of kStripOut output columns
-  int nblocks;  // equal ranges of the nstrips * ny strip-rows, one per block
+  int nunits;   // groups of strips_per_block(storage, scheme) neighbouring strips
+  int nblocks;  // equal ranges of the nunits * ny unit-rows, one per block
   int band;     // rows per band of the band-major strip-row order
   int scheme;   // 1: T2S2-FDLBM1 family (eq 2.23); 2: T2S2-FDLBM2 (eq 5.23)
   const double* wx;   // [nx][2][4] dt-scaled x weights (FP64)

@@ -32,14 +32,14 @@ namespace {
 // ---------------------------------------------------------------------------
 // Fused step.
 // ---------------------------------------------------------------------------
-// New-state stores.  FP64 and FP32 rows (448 and 224 bytes per wave) go out
-// as non-temporal (streaming) stores: the state is not read again in this
-// launch, and on this part they reach HBM faster than write-back stores.
-// The 16-bit rows (112 bytes, under one cache line) merge better in L2 and
-// use ordinary stores.
+// New-state stores.  FP64 rows (448 bytes per wave) go out as non-temporal
+// (streaming) stores: the state is not read again in this launch, and they
+// reach HBM faster than write-back stores.  The narrower FP32 and 16-bit
+// rows (224 and 112 bytes, not line-aligned) merge better in L2 and use
+// ordinary stores (measured: FP32 5% faster so).
 template <typename Store>
 __device__ inline void store_state(Store* p, Store v) {
-  if constexpr (std::is_same<Store, double>::value || std::is_same<Store, float>::value)
+  if constexpr (std::is_same<Store, double>::value)
     __builtin_nontemporal_store(v, p);
   else
     *p = v;
@@ -151,46 +151,58 @@ constexpr int kPPlanes = kScheme == 2 ? 2 * kQ - 1 : kQ;
 //     with f^{n+1} predicted by S = Q + dt L(Q) and unshifted with h = dt;
 //     L is linear, so the two gradients are taken as one, of T = f^n + R.
 template <typename Store, bool kForce, bool kWalls, int kScheme>
-__global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls, kScheme>)) void step_kernel(
+__global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWaves<Store, kForce, kWalls, kScheme>)) void step_kernel(
     StepParams p) {
   using Real = typename Cvt<Store>::R;
   constexpr int kNP = kPPlanes<kScheme>;
-  __shared__ Real ringP[kRing * kNP * kLanes];      // [slot][plane][lane]
-  __shared__ Real ringR[kRing * (kQ - 1) * kLanes];  // [slot][q-1][lane]
+  constexpr int kSB = strips_per_block(kStorageOf<Store>, kScheme);
+  constexpr int kThreads = step_threads(kStorageOf<Store>, kScheme);
+  constexpr int kSizeP = kRing * kNP * kLanes, kSizeR = kRing * (kQ - 1) * kLanes;
+  constexpr int kSizeT = kWalls ? (kQ - 1) * kLanes : 1;
+  __shared__ Real ringP_all[kSB * kSizeP];  // per strip: [slot][plane][lane]
+  __shared__ Real ringR_all[kSB * kSizeR];  // per strip: [slot][q-1][lane]
   // R of the top wall row ny-1, kept out of the ring: it is written (eq 3.10)
   // by the wave that computes row ny-2, in the same phase in which the ring
   // slot of row ny-1 still holds row ny-9 for the output row ny-7.
-  __shared__ Real topR[kWalls ? (kQ - 1) * kLanes : 1];
+  __shared__ Real topR_all[kSB * kSizeT];
 
   const int lane = threadIdx.x & (kLanes - 1);
-  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+  const int half = kSB == 1 ? 0 : wave / kRowsPerIter;  // which of the block's strips
+  const int t = kSB == 1 ? wave : wave % kRowsPerIter;  // which row of an iteration
+  Real* const ringP = ringP_all + half * kSizeP;
+  Real* const ringR = ringR_all + half * kSizeR;
+  Real* const topR = topR_all + half * kSizeT;
   const int nx = p.nx, ny = p.ny;
   const Store* __restrict__ src = static_cast<const Store*>(p.src);
   Store* __restrict__ dst = static_cast<Store*>(p.dst);
   const long long plane = p.plane;
 
-  for (int i = threadIdx.x; i < kRing * kNP * kLanes; i += kBlockThreads) ringP[i] = Real(0);
-  for (int i = threadIdx.x; i < kRing * (kQ - 1) * kLanes; i += kBlockThreads) ringR[i] = Real(0);
+  for (int i = threadIdx.x; i < kSB * kSizeP; i += kThreads) ringP_all[i] = Real(0);
+  for (int i = threadIdx.x; i < kSB * kSizeR; i += kThreads) ringR_all[i] = Real(0);
   if (kWalls)
-    for (int i = threadIdx.x; i < (kQ - 1) * kLanes; i += kBlockThreads) topR[i] = Real(0);
+    for (int i = threadIdx.x; i < kSB * kSizeT; i += kThreads) topR_all[i] = Real(0);
 
-  // Work: the rows are cut into bands of p.band rows; the strip-rows are
-  // ordered band by band, strip by strip within a band, row by row within a
-  // strip, and this order is cut into nblocks equal ranges (one per block,
-  // so every block does the same work).  With the band height equal to one
-  // block's share, a block owns one strip of one band, and the blocks of
-  // neighbouring strips start on the same row and march in step: the cache
-  // lines that two strips share (the halo columns) are fetched from HBM once
-  // and found in L2 by the second strip.  A range may run over a strip or
-  // band boundary; each piece is marched separately.  XCD-aware order: the
-  // grid is a multiple of 8 and blocks are dealt round-robin to the 8 XCDs,
-  // so block b runs on XCD b % 8; each XCD gets a contiguous run of ranges,
-  // i.e. neighbouring strips of a band share one L2.
+  // Work: a unit is kSB neighbouring strips, marched side by side by the
+  // block's kSB groups of four waves (a strip past the last column computes
+  // in its own rings and stores nothing).  The rows are cut into bands of
+  // p.band rows; the unit-rows are ordered band by band, unit by unit within
+  // a band, row by row within a unit, and this order is cut into nblocks
+  // equal ranges (one per block, so every block does the same work).  With
+  // the band height equal to one block's share, a block owns one unit of one
+  // band, and the blocks of neighbouring units start on the same row and
+  // march in step: the cache lines that two strips share (the halo columns)
+  // are fetched from HBM once and found in L1 or L2 by the other strip.  A
+  // range may run over a unit or band boundary; each piece is marched
+  // separately.  XCD-aware order: the grid is a multiple of 8 and blocks are
+  // dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8; each XCD
+  // gets a contiguous run of ranges, i.e. neighbouring units of a band share
+  // one L2.
   const int G = gridDim.x;
   const int L = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
   if (L >= p.nblocks) return;  // padding block: whole block, before any barrier
-  const long long total = static_cast<long long>(p.nstrips) * ny;
-  const long long band_pieces = static_cast<long long>(p.nstrips) * p.band;
+  const long long total = static_cast<long long>(p.nunits) * ny;
+  const long long band_pieces = static_cast<long long>(p.nunits) * p.band;
   long long beg = total * L / p.nblocks;
   const long long end = total * (L + 1) / p.nblocks;
 
@@ -199,7 +211,7 @@ __global__ __launch_bounds__(kBlockThreads, (kMinWaves<Store, kForce, kWalls, kS
     const long long rem = beg - b * band_pieces;
     const int r0 = b * p.band;
     const int hb = min(p.band, ny - r0);  // the last band may be shorter
-    const int strip = static_cast<int>(rem / hb);
+    const int strip = static_cast<int>(rem / hb) * kSB + half;
     const int y0 = r0 + static_cast<int>(rem % hb);
     const int y1 = static_cast<int>(min(static_cast<long long>(r0 + hb), y0 + (end - beg)));
     beg += y1 - y0;
@@ -648,7 +660,7 @@ void launch_fused(const StepParams& p, dim3 g, dim3 b, hipStream_t s, bool walls
 
 template <typename Store>
 hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
-  const dim3 g(grid), b(kBlockThreads);
+  const dim3 g(grid), b(step_threads(kStorageOf<Store>, p.scheme));
   const bool walls = !p.per_x || !p.per_y;
   if (p.scheme == 2)
     launch_fused<Store, 2>(p, g, b, s, walls);
@@ -695,14 +707,14 @@ int occupancy_s(bool force, bool walls) {
   hipError_t e;
   if (force)
     e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, step_kernel<Store, true, true, kScheme>, kBlockThreads, 0)
+                    &n, step_kernel<Store, true, true, kScheme>, step_threads(kStorageOf<Store>, kScheme), 0)
               : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, step_kernel<Store, true, false, kScheme>, kBlockThreads, 0);
+                    &n, step_kernel<Store, true, false, kScheme>, step_threads(kStorageOf<Store>, kScheme), 0);
   else
     e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, step_kernel<Store, false, true, kScheme>, kBlockThreads, 0)
+                    &n, step_kernel<Store, false, true, kScheme>, step_threads(kStorageOf<Store>, kScheme), 0)
               : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, step_kernel<Store, false, false, kScheme>, kBlockThreads, 0);
+                    &n, step_kernel<Store, false, false, kScheme>, step_threads(kStorageOf<Store>, kScheme), 0);
   return e == hipSuccess ? n : -1;
 }
 

@@ -276,3 +276,45 @@ def test_fdlbm2_fp32_error_vs_oracle():
     err = _rel(np.stack([u, v]), np.stack([ur, vr]))
     print(f"    f32 FDLBM2: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
     assert err <= 3e-5
+
+
+# -------------------------------- FP32 storage: two strips per block
+
+@pytest.mark.parametrize("blocks", ["8", "24"])
+def test_fp32_walled_cavity_odd_strip_count(blocks, monkeypatch):
+    """FP32 storage marches two neighbouring strips per block; the 130x65
+    cavity has three strips, so one block carries a strip past the last
+    column (computes in its own rings, stores nothing).  Against the FP64
+    oracle within the FP32 form's error; the tiling does not change a bit."""
+    case = _ragged_cavity(0.8)
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 150)
+    _, ur, vr = oracle.moments(case, ref)
+    monkeypatch.setenv("T2S2_BLOCKS", blocks)
+    _, g, d, u, v = _gpu_run(case, phi0, 150, storage="f32")
+    err = _rel(np.stack([u, v]), np.stack([ur, vr]))
+    print(f"    f32 cavity130x65: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
+    assert err <= 1e-4
+    monkeypatch.setenv("T2S2_BLOCKS", "64")
+    _, g2, *_ = _gpu_run(case, phi0, 150, storage="f32")
+    assert np.array_equal(g, g2)
+
+
+def test_fp32_periodic_tiling_invariance():
+    """FP32 periodic 150x70 (three strips across the seam): bitwise the same
+    state for three block counts."""
+    case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.7, eta=0.05)
+    phi0 = oracle.init(case) + W.random_state((9, 70, 150), 1e-5, 8)
+    outs = []
+    for blocks in ("8", "16", "40"):
+        os.environ["T2S2_BLOCKS"] = blocks
+        try:
+            _, g, *_ = _gpu_run(case, phi0, 60, storage="f32")
+        finally:
+            del os.environ["T2S2_BLOCKS"]
+        outs.append(g)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    ref = oracle.run(case, phi0, 60)
+    _, ur, vr = oracle.moments(case, ref)
+    _, u, v = oracle.moments(case, outs[0])
+    assert _rel(np.stack([u, v]), np.stack([ur, vr])) <= 1e-4
