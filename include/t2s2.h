@@ -208,6 +208,42 @@ int t2s2_adjoint_init_macro(t2s2_ctx* ctx, const void* lam0, const double* rho,
 int t2s2_adjoint_read(t2s2_ctx* ctx, const void* lam, double* out);
 int t2s2_adjoint_load(t2s2_ctx* ctx, const double* in, void* lam);
 
+/* ---- Von Neumann stability maps (Sec. 2C) -----------------------------
+ * For each point (omega_i, r_i) -- omega = dt / tau, r = dt / dx on a
+ * uniform mesh, xi = 1 -- the largest spectral radius, over a grid of modes
+ * k, of the growth matrix G(k) (9 x 9) of a perturbation f' e^{i k.x} about
+ * the uniform equilibrium f^eq(rho = 1, u):
+ *   T2S2_STAB_PAPER  eq 4.7 for the (B~2, B-2) family (b2tilde, b2bar), with
+ *                    the advection symbol applied from the left;
+ *   T2S2_STAB_FDLBM1 the exact linearisation of the step of eq 2.23 with
+ *                    h = A dt (the step t2s2_step takes for T2S2_FDLBM1);
+ *   T2S2_STAB_FDLBM2 the exact linearisation of the eq 5.23 step.
+ * S is the symbol of the mixed difference (eq 4.8 with the imaginary unit
+ * in its exponentials).  Modes: theta_y = k_y dx in [0, pi] (nk points);
+ * theta_x in [0, pi] (nk points) or, with full_kx, in [-pi, pi] (2 nk - 1
+ * points), which with theta_y covers every mode up to conjugation.  The
+ * radius is ||G^m||^(1/m) at m = 2^squarings (relative error about
+ * ln(cond) / m).  omega, r, radius: device FP64 arrays of npoints.
+ * Asynchronous on `stream` (a hipStream_t, NULL = default). */
+#define T2S2_STAB_PAPER 0
+#define T2S2_STAB_FDLBM1 1
+#define T2S2_STAB_FDLBM2 2
+
+typedef struct t2s2_stability_params {
+  int model;       /* T2S2_STAB_PAPER, T2S2_STAB_FDLBM1, T2S2_STAB_FDLBM2 */
+  double eta;      /* upwind weight, in [0, 1] */
+  double A;        /* intermediate stage (T2S2_STAB_FDLBM1), in [0, 1] */
+  double b2bar;    /* B-2 of eq 4.7 (T2S2_STAB_PAPER) */
+  double b2tilde;  /* B~2 of eq 4.7 (T2S2_STAB_PAPER) */
+  double u[2];     /* velocity of the uniform state */
+  int nk;          /* modes per half axis, 2..257 */
+  int full_kx;     /* 1: theta_x in [-pi, pi]; 0: [0, pi] */
+  int squarings;   /* 1..60 */
+} t2s2_stability_params;
+
+int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, const double* r,
+                       int npoints, double* radius, void* stream);
+
 void t2s2_destroy(t2s2_ctx* ctx);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -50,6 +50,24 @@ class Config(ctypes.Structure):
     ]
 
 
+class StabilityParams(ctypes.Structure):
+    """Mirror of struct t2s2_stability_params (include/t2s2.h)."""
+
+    _fields_ = [
+        ("model", ctypes.c_int),
+        ("eta", ctypes.c_double),
+        ("A", ctypes.c_double),
+        ("b2bar", ctypes.c_double),
+        ("b2tilde", ctypes.c_double),
+        ("u", ctypes.c_double * 2),
+        ("nk", ctypes.c_int),
+        ("full_kx", ctypes.c_int),
+        ("squarings", ctypes.c_int),
+    ]
+
+
+STAB_MODELS = {"paper": 0, "fdlbm1": 1, "fdlbm2": 2}
+
 _lib = None
 
 
@@ -94,6 +112,7 @@ def load_library(path: str = LIB_PATH):
         "t2s2_adjoint_init_macro": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "t2s2_adjoint_read": (i, [vp, vp, vp]),
         "t2s2_adjoint_load": (i, [vp, vp, vp]),
+        "t2s2_stability_map": (i, [ctypes.POINTER(StabilityParams), vp, vp, i, vp, vp]),
         "t2s2_destroy": (None, [vp]),
         "t2s2_last_error": (ctypes.c_char_p, []),
     }
@@ -113,7 +132,7 @@ def exported_symbols() -> Sequence[str]:
             "t2s2_diagnostics", "t2s2_omega", "t2s2_adjoint_state_bytes",
             "t2s2_adjoint_scratch_bytes", "t2s2_bind_adjoint", "t2s2_adjoint_seed_velocity",
             "t2s2_adjoint_step", "t2s2_adjoint_init_macro", "t2s2_adjoint_read",
-            "t2s2_adjoint_load", "t2s2_destroy", "t2s2_last_error")
+            "t2s2_adjoint_load", "t2s2_stability_map", "t2s2_destroy", "t2s2_last_error")
 
 
 def _check(rc: int):
@@ -333,3 +352,28 @@ def context_for_case(case, storage="f64", device=None, stream=None, **overrides)
               storage=storage)
     kw.update(overrides)
     return Context(make_config(**kw), case.x, case.y, device=device, stream=stream)
+
+
+def stability_map(model, omega, r, *, eta, u=(0.0, 0.0), A=0.5, b2bar=0.5, b2tilde=0.0,
+                  nk=33, full_kx=True, squarings=30, device=None, stream=None):
+    """Largest spectral radius of the growth matrix over the mode grid for
+    each (omega[i], r[i]) (t2s2_stability_map); returns a device tensor."""
+    import torch
+
+    lib = load_library()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    w = torch.as_tensor(omega, dtype=torch.float64, device=dev).contiguous().reshape(-1)
+    rr = torch.as_tensor(r, dtype=torch.float64, device=dev).contiguous().reshape(-1)
+    if w.shape != rr.shape:
+        raise ValueError("omega and r must have the same number of points")
+    out = torch.empty_like(w)
+    prm = StabilityParams()
+    prm.model = STAB_MODELS[model] if isinstance(model, str) else int(model)
+    prm.eta, prm.A, prm.b2bar, prm.b2tilde = float(eta), float(A), float(b2bar), float(b2tilde)
+    prm.u[0], prm.u[1] = float(u[0]), float(u[1])
+    prm.nk, prm.full_kx, prm.squarings = int(nk), int(bool(full_kx)), int(squarings)
+    with torch.cuda.device(dev):
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        _check(lib.t2s2_stability_map(ctypes.byref(prm), w.data_ptr(), rr.data_ptr(), w.numel(),
+                                      out.data_ptr(), st.cuda_stream))
+    return out

@@ -666,6 +666,43 @@ int t2s2_adjoint_load(t2s2_ctx* c, const double* in, void* lam) {
   return T2S2_OK;
 }
 
+int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, const double* r,
+                       int npoints, double* radius, void* stream) {
+  g_last_error.clear();
+  if (!prm) return fail(T2S2_ERR_INVALID_ARG, "NULL parameters");
+  if (prm->model < T2S2_STAB_PAPER || prm->model > T2S2_STAB_FDLBM2)
+    return fail(T2S2_ERR_INVALID_ARG, "unknown stability model");
+  if (!(prm->eta >= 0.0 && prm->eta <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "eta not in [0,1]");
+  if (!(prm->A >= 0.0 && prm->A <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "A not in [0,1]");
+  if (!std::isfinite(prm->b2bar) || !std::isfinite(prm->b2tilde) || !std::isfinite(prm->u[0]) ||
+      !std::isfinite(prm->u[1]))
+    return fail(T2S2_ERR_INVALID_ARG, "non-finite parameter");
+  if (prm->nk < 2 || prm->nk > 257) return fail(T2S2_ERR_INVALID_ARG, "nk not in [2, 257]");
+  if (prm->squarings < 1 || prm->squarings > 60)
+    return fail(T2S2_ERR_INVALID_ARG, "squarings not in [1, 60]");
+  if (npoints < 0) return fail(T2S2_ERR_INVALID_ARG, "npoints < 0");
+  if (npoints == 0) return T2S2_OK;
+  if (!omega || !r || !radius) return fail(T2S2_ERR_INVALID_ARG, "NULL array");
+  StabArgs a{};
+  a.model = prm->model;
+  a.eta = prm->eta;
+  a.A = prm->A;
+  a.b2bar = prm->b2bar;
+  a.b2tilde = prm->b2tilde;
+  a.ux = prm->u[0];
+  a.uy = prm->u[1];
+  const double pi = 3.14159265358979323846;
+  a.nky = prm->nk;
+  a.dthy = pi / (prm->nk - 1);
+  a.dthx = a.dthy;
+  a.nkx = prm->full_kx ? 2 * prm->nk - 1 : prm->nk;
+  a.thx0 = prm->full_kx ? -pi : 0.0;
+  a.squarings = prm->squarings;
+  hipError_t e = launch_stability(a, omega, r, npoints, radius, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "stability map");
+  return T2S2_OK;
+}
+
 void t2s2_destroy(t2s2_ctx* c) { delete c; }
 
 }  // extern "C"

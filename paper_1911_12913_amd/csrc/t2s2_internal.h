@@ -88,6 +88,17 @@ struct AuxParams {
   const double* jy;     // [ny]
 };
 
+// Von Neumann stability maps (t2s2_stability.hip).
+struct StabArgs {
+  int model;  // 0: eq 4.7; 1: eq 2.23 step, exact; 2: eq 5.23 step, exact
+  double eta, A, b2bar, b2tilde, ux, uy;
+  int nkx, nky;             // k grid: theta_x = thx0 + i dthx, theta_y = j dthy
+  double thx0, dthx, dthy;
+  int squarings;
+};
+hipError_t launch_stability(const StabArgs& a, const double* omega, const double* r, int npoints,
+                            double* radius, hipStream_t s);
+
 // Adjoint of the step (t2s2_adjoint.hip).  Real-typed buffers (FP64 for
 // T2S2_F64 storage, FP32 otherwise) share the state's pitched layout.
 struct AdjParams {

@@ -129,3 +129,24 @@ def test_infinite_nu_is_collisionless():
     rc, h = _create(_good_cfg(nu=math.inf), _axis(20), _axis(20))
     assert rc == t2s2.OK
     lib.t2s2_destroy(h)
+
+
+def test_stability_map_argument_checks_without_device():
+    """Invalid parameters are refused before any device call; an empty map
+    is a no-op."""
+    lib = t2s2.load_library()
+
+    def prm(**kw):
+        p = t2s2.StabilityParams()
+        p.model, p.eta, p.A, p.b2bar, p.b2tilde = 1, 0.1, 0.5, 0.5, 0.0
+        p.nk, p.full_kx, p.squarings = 9, 1, 30
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return ctypes.byref(p)
+
+    assert lib.t2s2_stability_map(prm(), None, None, 0, None, None) == t2s2.OK
+    for bad in (dict(model=3), dict(eta=1.5), dict(A=-0.1), dict(nk=1), dict(nk=2000),
+                dict(squarings=0), dict(squarings=61), dict(b2bar=math.nan)):
+        assert lib.t2s2_stability_map(prm(**bad), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
+    assert lib.t2s2_stability_map(prm(), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
+    assert lib.t2s2_stability_map(None, None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
