@@ -318,3 +318,70 @@ def test_fp32_periodic_tiling_invariance():
     ref = oracle.run(case, phi0, 60)
     _, ur, vr = oracle.moments(case, ref)
     assert _rel(vels[0], np.stack([ur, vr])) <= 1e-4
+
+
+# ------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("walled", [True, False])
+def test_minimum_mesh_5x5(walled):
+    """The smallest mesh the library accepts (5 x 5): walled cavity (three
+    interior nodes per axis) and periodic, 60 steps, against the oracle."""
+    if walled:
+        case = W.cavity_case(4, lid=0.1, re=100.0, cfl=0.5, eta=0.1, noise=1e-4, seed=5)
+    else:
+        case = W.tgv_case(5, 5, u0=0.02, nu=0.05, cfl=0.5, eta=0.1)
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 60)
+    _, g, d, u, v = _gpu_run(case, phi0, 60)
+    _compare(case, g, d, u, v, ref)
+
+
+def test_zero_steps_is_identity():
+    case = W.cavity_case(32, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
+    phi0 = oracle.init(case)
+    ctx, g, *_ = _gpu_run(case, phi0, 0)
+    assert ctx.steps_taken == 0
+    assert np.array_equal(g, phi0)
+
+
+@pytest.mark.parametrize("eta", [0.0, 1.0])
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_eta_extremes_walled(eta, scheme):
+    """Pure central (eta = 0) and pure second-order upwind (eta = 1)
+    differences on the walled ragged cavity, both schemes, 100 steps."""
+    case = _ragged_cavity(0.5)
+    case.eta = eta
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 100, scheme=scheme)
+    _, g, d, u, v = _gpu_run(case, phi0, 100, scheme=scheme)
+    _compare(case, g, d, u, v, ref)
+
+
+def test_largest_mesh_uniform_flow_is_a_fixed_point():
+    """16384 x 16384 periodic FP64 (two 19 GB state buffers): a uniform
+    flow at equilibrium is a fixed point of the step (all differences
+    vanish), so after 4 steps rho and u are unchanged up to rounding."""
+    n = 16384
+    dev = "cuda:0"
+    x = np.arange(n) * (2 * math.pi / n)
+    cfg = t2s2.make_config(nu=1e-3, cfl=0.9, eta=0.01, periodic_x=True, periodic_y=True,
+                           period_x=2 * math.pi, period_y=2 * math.pi)
+    print(f"[gpu] uniform flow {n}x{n} FP64", flush=True)
+    ctx = t2s2.Context(cfg, x, x, device=dev)
+    U, V = 0.05, -0.03
+    rho = torch.ones((n, n), dtype=torch.float64, device=dev)
+    ctx.init_macro(rho, torch.full_like(rho, U), torch.full_like(rho, V))
+    del rho
+    ctx.step(4)
+    d, u, v = ctx.moments()
+    torch.cuda.synchronize()
+    du = float((u - U).abs().max())
+    dv = float((v - V).abs().max())
+    dd = float(d.abs().max())
+    print(f"    max |u - U| {du:.2e}  |v - V| {dv:.2e}  |rho - 1| {dd:.2e}", flush=True)
+    assert du <= 1e-15 and dv <= 1e-15 and dd <= 1e-15
+    diag = ctx.diagnostics()
+    assert diag["nonfinite"] == 0
+    ctx.close()
+    del ctx, d, u, v
+    torch.cuda.empty_cache()
