@@ -12,11 +12,14 @@
 // adjoint runs [6]..[1] in reverse with the transposed stencil (a gather
 // over the nodes whose stencil reads this one, with their weights) and the
 // transposed moment Jacobians of the equilibrium.  Every kernel is
-// node-parallel over materialised intermediates; the wall-to-fluid scatter
-// of [4] and [6] is gathered at the fluid node, so no atomics are needed and
-// the result is deterministic.  d/d omega of the step (omega = dt / tau)
-// enters only through the pointwise coefficients; its inner products with
-// the adjoints are reduced in a fixed block order.
+// node-parallel: P and S are recomputed into scratch; [6'] (walled domains
+// only; otherwise the output adjoint is lam_{n+1} itself) writes mu; [5'-3']
+// gather L^T mu on the fly and write lamS; [2'-1'] gather L^T lamS on the
+// fly and write lam_n.  The wall-to-fluid scatter of [4] and [6] is gathered
+// at the fluid node, so no atomics are needed and the result is
+// deterministic.  d/d omega of the step (omega = dt / tau) enters only
+// through the pointwise coefficients; its inner products with the adjoints
+// are reduced in a fixed block order.
 #include <hip/hip_runtime.h>
 
 #include "t2s2_device.h"
@@ -302,30 +305,22 @@ __device__ inline Real stencil_T(const AdjParams& a, const Real* in, const Real*
   return acc;
 }
 
-// ---- [5'] lamR = L^T mu at every node (population 0: no stencil).
+// ---- [5'] + [4'] + [3'] lamS at interior nodes (zero on walls), with the
+// d/d omega inner product of the R stage.  The adjoint of R, L^T mu (no
+// stencil for population 0), is gathered here for the node and for the
+// wall nodes extrapolated from it.
 template <typename Real>
-__global__ __launch_bounds__(256) void adj_R(AdjParams a) {
-  const Real* mu = static_cast<const Real*>(a.mu);
-  Real* lamR = static_cast<Real*>(a.lamR);
-  const Real* WX = wtab_x<Real>(a);
-  const Real* WY = wtab_y<Real>(a);
-  NODE_LOOP(a) {
-    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
-    const long long off = static_cast<long long>(y) * a.pitch + x;
-    lamR[off] = Real(0);
-#pragma unroll
-    for (int q = 1; q < kQ; ++q) lamR[q * a.plane + off] = stencil_T(a, mu, WX, WY, q, x, y);
-  }
-}
-
-// ---- [4'] + [3'] lamS at interior nodes (zero on walls), with the
-// d/d omega inner product of the R stage.
-template <typename Real>
-__global__ __launch_bounds__(256) void adj_S(AdjParams a, double* partial) {
+__global__ __launch_bounds__(256) void adj_S(AdjParams a, const Real* mu, double* partial) {
   __shared__ double red[256];
   const Real* S = static_cast<const Real*>(a.S);
-  const Real* lamR = static_cast<const Real*>(a.lamR);
   Real* lamS = static_cast<Real*>(a.lamS);
+  const Real* WX = wtab_x<Real>(a);
+  const Real* WY = wtab_y<Real>(a);
+  auto lam_R = [&](int x, int y, Real out[kQ]) {
+    out[0] = Real(0);
+#pragma unroll
+    for (int q = 1; q < kQ; ++q) out[q] = stencil_T(a, mu, WX, WY, q, x, y);
+  };
   double dw = 0.0;
   NODE_LOOP(a) {
     const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
@@ -337,16 +332,15 @@ __global__ __launch_bounds__(256) void adj_S(AdjParams a, double* partial) {
     }
     Real s[kQ], lr[kQ];
     load9(S, a.plane, off, s);
-    load9(lamR, a.plane, off, lr);
+    lam_R(x, y, lr);
     double rho, ux, uy;
     node_rho_u(s, rho, ux, uy);
     Real ls[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) ls[q] = Real(0);
     for_wall_dependents(a, x, y, [&](int bx, int by) {
-      const long long boff = static_cast<long long>(by) * a.pitch + bx;
       Real lb[kQ];
-      load9(lamR, a.plane, boff, lb);
+      lam_R(bx, by, lb);
       double ub, vb;
       wall_vel(a, bx, by, ub, vb);
       double sa, sbx, sby;
@@ -377,36 +371,17 @@ __global__ __launch_bounds__(256) void adj_S(AdjParams a, double* partial) {
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// ---- [2'] lamP = [interior] lamS + A L^T lamS at every node.  Written
-// into the P buffer (P is not needed after [2]).
-template <typename Real>
-__global__ __launch_bounds__(256) void adj_P(AdjParams a) {
-  const Real* lamS = static_cast<const Real*>(a.lamS);
-  Real* lamP = static_cast<Real*>(a.P);
-  const Real* WX = wtab_x<Real>(a);
-  const Real* WY = wtab_y<Real>(a);
-  NODE_LOOP(a) {
-    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
-    const long long off = static_cast<long long>(y) * a.pitch + x;
-    const bool in = interior(a, x, y);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      Real v = in ? lamS[q * a.plane + off] : Real(0);
-      if (q != 0) v += static_cast<Real>(a.A) * stencil_T(a, lamS, WX, WY, q, x, y);
-      lamP[q * a.plane + off] = v;
-    }
-  }
-}
-
-// ---- [1'] lam_n from lamP and lamQ (= mu), with the d/d omega inner
-// products of the P and Q stages.
+// ---- [2'] + [1'] lam_n from lamP = [interior] lamS + A L^T lamS and
+// lamQ (= mu), with the d/d omega inner products of the P and Q stages.
 template <typename Store>
 __global__ __launch_bounds__(256) void adj_g(AdjParams a, const Store* g,
+                                              const typename Cvt<Store>::R* lamQ,
                                               typename Cvt<Store>::R* lam_out, double* partial) {
   using Real = typename Cvt<Store>::R;
   __shared__ double red[256];
-  const Real* lamP = static_cast<const Real*>(a.P);
-  const Real* lamQ = static_cast<const Real*>(a.mu);
+  const Real* lamS = static_cast<const Real*>(a.lamS);
+  const Real* WX = wtab_x<Real>(a);
+  const Real* WY = wtab_y<Real>(a);
   double dw = 0.0;
   NODE_LOOP(a) {
     const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
@@ -414,7 +389,13 @@ __global__ __launch_bounds__(256) void adj_g(AdjParams a, const Store* g,
     Real v[kQ], lp[kQ], lq[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * a.plane + off]);
-    load9(lamP, a.plane, off, lp);
+    const bool in = interior(a, x, y);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      Real lv = in ? lamS[q * a.plane + off] : Real(0);
+      if (q != 0) lv += static_cast<Real>(a.A) * stencil_T(a, lamS, WX, WY, q, x, y);
+      lp[q] = lv;
+    }
     load9(lamQ, a.plane, off, lq);
     double rho, ux, uy;
     node_rho_u(v, rho, ux, uy);
@@ -519,22 +500,29 @@ hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp,
                           double* partial, double* accum, hipStream_t s) {
   using Real = typename Cvt<Store>::R;
   const int G = kDiagBlocks;  // fixed grid: the reductions are deterministic
-  // f~^{n+1} again, into the scratch state (the walls' adjoint needs its
-  // moments at the fluid nodes).
-  StepParams fwd = sp;
-  fwd.src = state_n;
-  fwd.dst = a.next;
-  hipError_t e = launch_step(storage, fwd, step_grid, s);
-  if (e != hipSuccess) return e;
+  const bool walls = !a.per_x || !a.per_y;
+  const Real* mu = static_cast<const Real*>(lam_np1);
+  hipError_t e;
+  if (walls) {
+    // f~^{n+1} again, into the scratch state: the walls' adjoint needs its
+    // moments at the fluid nodes.  Without walls the output adjoint mu is
+    // lam_np1 itself.
+    StepParams fwd = sp;
+    fwd.src = state_n;
+    fwd.dst = a.next;
+    e = launch_step(storage, fwd, step_grid, s);
+    if (e != hipSuccess) return e;
+  }
   const Store* g = static_cast<const Store*>(state_n);
   hipLaunchKernelGGL(adj_fwd_P<Store>, dim3(G), dim3(256), 0, s, a, g);
   hipLaunchKernelGGL(adj_fwd_S<Real>, dim3(G), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(adj_out_walls<Store>, dim3(G), dim3(256), 0, s, a,
-                     static_cast<const Store*>(a.next), static_cast<const Real*>(lam_np1));
-  hipLaunchKernelGGL(adj_R<Real>, dim3(G), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(adj_S<Real>, dim3(G), dim3(256), 0, s, a, partial);
-  hipLaunchKernelGGL(adj_P<Real>, dim3(G), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(adj_g<Store>, dim3(G), dim3(256), 0, s, a, g, static_cast<Real*>(lam_n),
+  if (walls) {
+    hipLaunchKernelGGL(adj_out_walls<Store>, dim3(G), dim3(256), 0, s, a,
+                       static_cast<const Store*>(a.next), mu);
+    mu = static_cast<const Real*>(a.mu);
+  }
+  hipLaunchKernelGGL(adj_S<Real>, dim3(G), dim3(256), 0, s, a, mu, partial);
+  hipLaunchKernelGGL(adj_g<Store>, dim3(G), dim3(256), 0, s, a, g, mu, static_cast<Real*>(lam_n),
                      partial + G);
   if (accum) hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, 2 * G, accum);
   return hipGetLastError();

@@ -554,7 +554,7 @@ size_t t2s2_adjoint_state_bytes(const t2s2_ctx* c) {
 
 size_t t2s2_adjoint_scratch_bytes(const t2s2_ctx* c) {
   if (!c) return 0;
-  return 5 * align256(t2s2_adjoint_state_bytes(c)) + align256(t2s2_state_bytes(c)) +
+  return 4 * align256(t2s2_adjoint_state_bytes(c)) + align256(t2s2_state_bytes(c)) +
          align256(2 * kDiagBlocks * sizeof(double));
 }
 
@@ -599,10 +599,9 @@ int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
   a.P = p;
   a.S = p + ab;
   a.mu = p + 2 * ab;
-  a.lamR = p + 3 * ab;
-  a.lamS = p + 4 * ab;
-  a.next = p + 5 * ab;
-  c->adj_partial = reinterpret_cast<double*>(p + 5 * ab + align256(t2s2_state_bytes(c)));
+  a.lamS = p + 3 * ab;
+  a.next = p + 4 * ab;
+  c->adj_partial = reinterpret_cast<double*>(p + 4 * ab + align256(t2s2_state_bytes(c)));
   c->adj_bound = true;
   return T2S2_OK;
 }

@@ -113,12 +113,11 @@ struct AdjParams {
   double cPg, cPe, cQg, cQe, cRs, cRe;
   double dcPg, dcQg, dcRs;  // d/d omega of cPg, cQg, cRs
   double uw[4][2];
-  void* P;     // P, then the adjoint of P
+  void* P;     // P
   void* S;     // S
-  void* mu;    // adjoint of the interior output (= adjoint of Q)
-  void* lamR;  // adjoint of R
+  void* mu;    // adjoint of the interior output (= adjoint of Q); walled domains
   void* lamS;  // adjoint of S
-  void* next;  // f~^{n+1} recomputed (storage type)
+  void* next;  // f~^{n+1} recomputed (storage type); walled domains
 };
 
 constexpr int kDiagBlocks = 512;
