@@ -12,8 +12,9 @@
 // adjoint runs [6]..[1] in reverse with the transposed stencil (a gather
 // over the nodes whose stencil reads this one, with their weights) and the
 // transposed moment Jacobians of the equilibrium.  Every kernel is
-// node-parallel: P and S are recomputed into scratch; [6'] (walled domains
-// only; otherwise the output adjoint is lam_{n+1} itself) writes mu; [5'-3']
+// node-parallel: S comes from a recompute of the fused step that stores it
+// as a side output; [6'] (walled domains only; otherwise the output adjoint
+// is lam_{n+1} itself) writes mu; [5'-3']
 // gather L^T mu on the fly and write lamS; [2'-1'] gather L^T lamS on the
 // fly and write lam_n.  The wall-to-fluid scatter of [4] and [6] is gathered
 // at the fluid node, so no atomics are needed and the result is
@@ -172,67 +173,6 @@ template <typename T>
 __device__ inline void load9(const T* base, long long plane, long long off, T v[kQ]) {
 #pragma unroll
   for (int q = 0; q < kQ; ++q) v[q] = base[q * plane + off];
-}
-
-// ---- [1] forward recompute: P at all nodes.
-template <typename Store>
-__global__ __launch_bounds__(256) void adj_fwd_P(AdjParams a, const Store* g) {
-  using Real = typename Cvt<Store>::R;
-  Real* P = static_cast<Real*>(a.P);
-  NODE_LOOP(a) {
-    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
-    const long long off = static_cast<long long>(y) * a.pitch + x;
-    Real v[kQ];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * a.plane + off]);
-    double rho, ux, uy;
-    node_rho_u(v, rho, ux, uy);
-    Real feq[kQ];
-    feq_dev(rho - 1.0, rho, ux, uy, feq);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q)
-      P[q * a.plane + off] =
-          static_cast<Real>(a.cPg) * v[q] + static_cast<Real>(a.cPe) * feq[q];
-  }
-}
-
-// ---- [2] forward recompute: S = P + A L(P) at interior nodes.
-template <typename Real>
-__global__ __launch_bounds__(256) void adj_fwd_S(AdjParams a) {
-  const Real* P = static_cast<const Real*>(a.P);
-  Real* S = static_cast<Real*>(a.S);
-  const Real* WX = wtab_x<Real>(a);
-  const Real* WY = wtab_y<Real>(a);
-  NODE_LOOP(a) {
-    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
-    const long long off = static_cast<long long>(y) * a.pitch + x;
-    if (!interior(a, x, y)) {
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) S[q * a.plane + off] = Real(0);
-      continue;
-    }
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      Real acc = Real(0);
-      if (ex_of(q) != 0) {
-        const int s = ex_of(q) > 0 ? 0 : 1;
-        for (int k = 0; k < kTaps; ++k) {
-          const int xx = along(x, tap_offset(s, k), a.nx, a.per_x);
-          const Real w = WX[x * kWeightsPerNode + s * kTaps + k];
-          if (xx >= 0) acc += w * P[q * a.plane + static_cast<long long>(y) * a.pitch + xx];
-        }
-      }
-      if (ey_of(q) != 0) {
-        const int s = ey_of(q) > 0 ? 0 : 1;
-        for (int k = 0; k < kTaps; ++k) {
-          const int yy = along(y, tap_offset(s, k), a.ny, a.per_y);
-          const Real w = WY[y * kWeightsPerNode + s * kTaps + k];
-          if (yy >= 0) acc += w * P[q * a.plane + static_cast<long long>(yy) * a.pitch + x];
-        }
-      }
-      S[q * a.plane + off] = P[q * a.plane + off] + static_cast<Real>(a.A) * acc;
-    }
-  }
 }
 
 // ---- [6'] mu = adjoint of the interior output including the wall rows
@@ -502,21 +442,17 @@ hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp,
   const int G = kDiagBlocks;  // fixed grid: the reductions are deterministic
   const bool walls = !a.per_x || !a.per_y;
   const Real* mu = static_cast<const Real*>(lam_np1);
-  hipError_t e;
-  if (walls) {
-    // f~^{n+1} again, into the scratch state: the walls' adjoint needs its
-    // moments at the fluid nodes.  Without walls the output adjoint mu is
-    // lam_np1 itself.
-    StepParams fwd = sp;
-    fwd.src = state_n;
-    fwd.dst = a.next;
-    e = launch_step(storage, fwd, step_grid, s);
-    if (e != hipSuccess) return e;
-  }
+  // The step again from state_n, into the scratch state (the walls' adjoint
+  // needs its moments at the fluid nodes), storing S as it goes.
+  StepParams fwd = sp;
+  fwd.src = state_n;
+  fwd.dst = a.next;
+  fwd.save_s = a.S;
+  hipError_t e = launch_step_save_s(storage, fwd, step_grid, s);
+  if (e != hipSuccess) return e;
   const Store* g = static_cast<const Store*>(state_n);
-  hipLaunchKernelGGL(adj_fwd_P<Store>, dim3(G), dim3(256), 0, s, a, g);
-  hipLaunchKernelGGL(adj_fwd_S<Real>, dim3(G), dim3(256), 0, s, a);
   if (walls) {
+    // Without walls the output adjoint mu is lam_np1 itself.
     hipLaunchKernelGGL(adj_out_walls<Store>, dim3(G), dim3(256), 0, s, a,
                        static_cast<const Store*>(a.next), mu);
     mu = static_cast<const Real*>(a.mu);

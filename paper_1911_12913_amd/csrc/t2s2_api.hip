@@ -554,7 +554,7 @@ size_t t2s2_adjoint_state_bytes(const t2s2_ctx* c) {
 
 size_t t2s2_adjoint_scratch_bytes(const t2s2_ctx* c) {
   if (!c) return 0;
-  return 4 * align256(t2s2_adjoint_state_bytes(c)) + align256(t2s2_state_bytes(c)) +
+  return 3 * align256(t2s2_adjoint_state_bytes(c)) + align256(t2s2_state_bytes(c)) +
          align256(2 * kDiagBlocks * sizeof(double));
 }
 
@@ -596,12 +596,11 @@ int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
   }
   char* p = static_cast<char*>(scratch);
   const size_t ab = align256(t2s2_adjoint_state_bytes(c));
-  a.P = p;
-  a.S = p + ab;
-  a.mu = p + 2 * ab;
-  a.lamS = p + 3 * ab;
-  a.next = p + 4 * ab;
-  c->adj_partial = reinterpret_cast<double*>(p + 4 * ab + align256(t2s2_state_bytes(c)));
+  a.S = p;
+  a.mu = p + ab;
+  a.lamS = p + 2 * ab;
+  a.next = p + 3 * ab;
+  c->adj_partial = reinterpret_cast<double*>(p + 3 * ab + align256(t2s2_state_bytes(c)));
   c->adj_bound = true;
   return T2S2_OK;
 }

@@ -54,6 +54,7 @@ struct StepParams {
   int nblocks;  // equal ranges of the nunits * ny unit-rows, one per block
   int band;     // rows per band of the band-major strip-row order
   int scheme;   // 1: T2S2-FDLBM1 family (eq 2.23); 2: T2S2-FDLBM2 (eq 5.23)
+  void* save_s; // adjoint recompute only: S in the arithmetic type, else NULL
   const double* wx;   // [nx][2][4] dt-scaled x weights (FP64)
   const double* wy;   // [ny][2][4]
   const float* wx32;  // same in FP32
@@ -113,11 +114,10 @@ struct AdjParams {
   double cPg, cPe, cQg, cQe, cRs, cRe;
   double dcPg, dcQg, dcRs;  // d/d omega of cPg, cQg, cRs
   double uw[4][2];
-  void* P;     // P
-  void* S;     // S
+  void* S;     // S, from the recompute of the step
   void* mu;    // adjoint of the interior output (= adjoint of Q); walled domains
   void* lamS;  // adjoint of S
-  void* next;  // f~^{n+1} recomputed (storage type); walled domains
+  void* next;  // f~^{n+1} recomputed (storage type)
 };
 
 constexpr int kDiagBlocks = 512;
@@ -125,6 +125,7 @@ constexpr int kDiagSlots = 8;
 
 // Launchers (t2s2_kernels.hip).  Return hipError_t of the launch.
 hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s);
+hipError_t launch_step_save_s(int storage, const StepParams& p, int grid, hipStream_t s);
 // Resident step-kernel blocks per CU for this variant (-1 on error).
 int step_blocks_per_cu(int storage, bool force, bool walls, int scheme);
 hipError_t launch_init_macro(int storage, const AuxParams& a, void* state, const double* rho,

@@ -145,12 +145,14 @@ template <int kScheme>
 constexpr int kPPlanes = kScheme == 2 ? 2 * kQ - 1 : kQ;
 
 // The fused step, templated on the storage type, the presence of a body
-// force, of walls, and on the scheme:
+// force, of walls, on the scheme, and on kSaveS (the discrete adjoint's
+// recompute: also store S = fbar(t*) at the interior nodes, into
+// p.save_s in the arithmetic type, [9][ny][pitch]):
 //   kScheme 1: T2S2-FDLBM1 family (eq 2.23; A = 0 is T1S2);
 //   kScheme 2: T2S2-FDLBM2 (eq 5.23): f~^{n+1} = Q + dt/2 (L(f^n) + L(f^{n+1}))
 //     with f^{n+1} predicted by S = Q + dt L(Q) and unshifted with h = dt;
 //     L is linear, so the two gradients are taken as one, of T = f^n + R.
-template <typename Store, bool kForce, bool kWalls, int kScheme>
+template <typename Store, bool kForce, bool kWalls, int kScheme, bool kSaveS = false>
 __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWaves<Store, kForce, kWalls, kScheme>)) void step_kernel(
     StepParams p) {
   using Real = typename Cvt<Store>::R;
@@ -336,6 +338,14 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
               for (int k2 = 0; k2 < kTaps; ++k2) acc += wyr[sy * kTaps + k2] * rb[k2 + sy][q * kLanes];
             }
             S[q] = q == 0 ? centre : centre + k.A * acc;
+          }
+          if (kSaveS && lane_o && col_interior && r >= y0 && r < y1) {
+            Real* sv = static_cast<Real*>(p.save_s);
+            const unsigned boff =
+                (static_cast<unsigned>(r) * static_cast<unsigned>(pitch) + static_cast<unsigned>(c)) *
+                static_cast<unsigned>(sizeof(Real));
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) *at_byte(sv + q * plane, boff) = S[q];
           }
           double s, jx, jy;
           moment_sums(S, s, jx, jy);
@@ -735,6 +745,25 @@ int step_blocks_per_cu(int storage, bool force, bool walls, int scheme) {
 
 hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s) {
   T2S2_DISPATCH(storage, return launch_step_t<Store>(p, grid, s));
+  return hipSuccess;
+}
+
+// The adjoint's recompute: the unforced T2S2-FDLBM1-family step from p.src
+// into p.dst, storing S into p.save_s as well.  The new state's wall nodes
+// are not set (the adjoint reads it at interior nodes only).
+template <typename Store>
+hipError_t launch_step_save_s_t(const StepParams& p, int grid, hipStream_t s) {
+  const dim3 g(grid), b(step_threads(kStorageOf<Store>, 1));
+  if (!p.per_x || !p.per_y)
+    hipLaunchKernelGGL((step_kernel<Store, false, true, 1, true>), g, b, 0, s, p);
+  else
+    hipLaunchKernelGGL((step_kernel<Store, false, false, 1, true>), g, b, 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_save_s(int storage, const StepParams& p, int grid, hipStream_t s) {
+  if (p.has_force || p.scheme != 1 || !p.save_s) return hipErrorInvalidValue;
+  T2S2_DISPATCH(storage, return launch_step_save_s_t<Store>(p, grid, s));
   return hipSuccess;
 }
 
