@@ -11,13 +11,13 @@
 // with L the dt-scaled mixed-difference operator -dt xi . grad.  The
 // adjoint runs [6]..[1] in reverse with the transposed stencil (a gather
 // over the nodes whose stencil reads this one, with their weights) and the
-// transposed moment Jacobians of the equilibrium.  Every kernel is
-// node-parallel: S comes from a recompute of the fused step that stores it
-// as a side output; [6'] (walled domains only; otherwise the output adjoint
-// is lam_{n+1} itself) writes mu; [5'-3']
-// gather L^T mu on the fly and write lamS; [2'-1'] gather L^T lamS on the
-// fly and write lam_n.  The wall-to-fluid scatter of [4] and [6] is gathered
-// at the fluid node, so no atomics are needed and the result is
+// transposed moment Jacobians of the equilibrium.  S comes from a recompute
+// of the fused step that stores it as a side output; [6'] (walled domains
+// only; otherwise the output adjoint is lam_{n+1} itself) writes mu node by
+// node; [5'] .. [1'] then run in one kernel that marches down strips of the
+// mesh like the forward step, holding lamS in an LDS ring, so neither lamR
+// nor lamS goes to memory.  The wall-to-fluid scatter of [4] and [6] is
+// gathered at the fluid node, so no atomics are needed and the result is
 // deterministic.  d/d omega of the step (omega = dt / tau) enters only
 // through the pointwise coefficients; its inner products with the adjoints
 // are reduced in a fixed block order.
@@ -218,142 +218,222 @@ __global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* n
   }
 }
 
-// Transposed stencil: out[m] = sum over interior nodes i whose stencil
-// reads m of w_k(i) in[i] (populations 1..8).
-template <typename Real>
-__device__ inline Real stencil_T(const AdjParams& a, const Real* in, const Real* WX,
-                                 const Real* WY, int q, int x, int y) {
-  Real acc = Real(0);
-  if (ex_of(q) != 0) {
-    const int s = ex_of(q) > 0 ? 0 : 1;
-    for (int k = 0; k < kTaps; ++k) {
-      const int xi = along(x, -tap_offset(s, k), a.nx, a.per_x);
-      if (xi >= 0 && interior(a, xi, y))
-        acc += WX[xi * kWeightsPerNode + s * kTaps + k] *
-               in[q * a.plane + static_cast<long long>(y) * a.pitch + xi];
-    }
-  }
-  if (ey_of(q) != 0) {
-    const int s = ey_of(q) > 0 ? 0 : 1;
-    for (int k = 0; k < kTaps; ++k) {
-      const int yi = along(y, -tap_offset(s, k), a.ny, a.per_y);
-      if (yi >= 0 && interior(a, x, yi))
-        acc += WY[yi * kWeightsPerNode + s * kTaps + k] *
-               in[q * a.plane + static_cast<long long>(yi) * a.pitch + x];
-    }
-  }
-  return acc;
-}
-
-// ---- [5'] + [4'] + [3'] lamS at interior nodes (zero on walls), with the
-// d/d omega inner product of the R stage.  The adjoint of R, L^T mu (no
-// stencil for population 0), is gathered here for the node and for the
-// wall nodes extrapolated from it.
-template <typename Real>
-__global__ __launch_bounds__(256) void adj_S(AdjParams a, const Real* mu, double* partial) {
-  __shared__ double red[256];
-  const Real* S = static_cast<const Real*>(a.S);
-  Real* lamS = static_cast<Real*>(a.lamS);
-  const Real* WX = wtab_x<Real>(a);
-  const Real* WY = wtab_y<Real>(a);
-  auto lam_R = [&](int x, int y, Real out[kQ]) {
-    out[0] = Real(0);
-#pragma unroll
-    for (int q = 1; q < kQ; ++q) out[q] = stencil_T(a, mu, WX, WY, q, x, y);
-  };
-  double dw = 0.0;
-  NODE_LOOP(a) {
-    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
-    const long long off = static_cast<long long>(y) * a.pitch + x;
-    if (!interior(a, x, y)) {
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) lamS[q * a.plane + off] = Real(0);
-      continue;
-    }
-    Real s[kQ], lr[kQ];
-    load9(S, a.plane, off, s);
-    lam_R(x, y, lr);
-    double rho, ux, uy;
-    node_rho_u(s, rho, ux, uy);
-    Real ls[kQ];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) ls[q] = Real(0);
-    for_wall_dependents(a, x, y, [&](int bx, int by) {
-      Real lb[kQ];
-      lam_R(bx, by, lb);
-      double ub, vb;
-      wall_vel(a, bx, by, ub, vb);
-      double sa, sbx, sby;
-      shift_ab(rho, ux, uy, ub, vb, lb, sa, sbx, sby);
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) lr[q] += lb[q];
-      through_moments(rho, ux, uy, sa, sbx, sby, ls, true);
-    });
-    Real feq[kQ];
-    feq_dev(rho - 1.0, rho, ux, uy, feq);
-    double fa, fbx, fby;
-    feq_ab(rho, ux, uy, lr, fa, fbx, fby);
-    const double cRe = a.cRe;
-    Real jt[kQ];
-    through_moments(rho, ux, uy, cRe * fa, cRe * fbx, cRe * fby, jt, false);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      lamS[q * a.plane + off] = ls[q] + static_cast<Real>(a.cRs) * lr[q] + jt[q];
-      dw += static_cast<double>(lr[q]) * a.dcRs * static_cast<double>(s[q] - feq[q]);
-    }
-  }
-  red[threadIdx.x] = dw;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-// ---- [2'] + [1'] lam_n from lamP = [interior] lamS + A L^T lamS and
-// lamQ (= mu), with the d/d omega inner products of the P and Q stages.
+// ---- [5'] .. [1'] in one march down strips of the mesh, with the layout
+// of the fused forward step: 64-lane strips with 56 output columns, four
+// waves, one row each per iteration.
+//   Phase A, row r = p0 + t: lamR = L^T mu (population 0 none) gathered
+//   from the interior nodes whose stencil reads (c, r) -- x taps as
+//   products w(source) mu(source) formed at the source lane and shifted
+//   in, y taps from the rows around -- then the transpose of the R stage
+//   and of the wall extrapolation of R ([4']: x-wall nodes' lamR from the
+//   neighbouring lane, y-wall rows' gathered on the fly, corners have none);
+//   lamS (zero off the interior) goes to an 8-row LDS ring.
+//   Phase B, row o = p0 - 2 + t: lamP = [interior] lamS + A L^T lamS from
+//   the ring, lamQ = mu, and lam_n through the P and Q stages.
+// The d/d omega partials sum over the nodes each lane outputs, once each.
 template <typename Store>
-__global__ __launch_bounds__(256) void adj_g(AdjParams a, const Store* g,
-                                              const typename Cvt<Store>::R* lamQ,
-                                              typename Cvt<Store>::R* lam_out, double* partial) {
+__global__ __launch_bounds__(256) void adj_strip(AdjParams a, const Store* g,
+                                                 const typename Cvt<Store>::R* mu,
+                                                 typename Cvt<Store>::R* lam_out, double* partial,
+                                                 int nstrips) {
   using Real = typename Cvt<Store>::R;
+  __shared__ Real ring[kRing * kQ * kLanes];  // lamS: [slot][q][lane]
   __shared__ double red[256];
-  const Real* lamS = static_cast<const Real*>(a.lamS);
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+  const int nx = a.nx, ny = a.ny;
+  const long long plane = a.plane;
+  const Real* S = static_cast<const Real*>(a.S);
   const Real* WX = wtab_x<Real>(a);
   const Real* WY = wtab_y<Real>(a);
+  const Real A = static_cast<Real>(a.A);
   double dw = 0.0;
-  NODE_LOOP(a) {
-    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
-    const long long off = static_cast<long long>(y) * a.pitch + x;
-    Real v[kQ], lp[kQ], lq[kQ];
+  for (int i = threadIdx.x; i < kRing * kQ * kLanes; i += 256) ring[i] = Real(0);
+
+  // lamR of population q at (c, y) from the rows around (y taps only): the
+  // wall rows' lamR, and the y part of the interior rows'.
+  auto lamR_y = [&](int q, int c, bool col_int, int y) {
+    Real acc = Real(0);
+    if (ey_of(q) == 0 || !col_int) return acc;
+    const int s = ey_of(q) > 0 ? 0 : 1;
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * a.plane + off]);
-    const bool in = interior(a, x, y);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      Real lv = in ? lamS[q * a.plane + off] : Real(0);
-      if (q != 0) lv += static_cast<Real>(a.A) * stencil_T(a, lamS, WX, WY, q, x, y);
-      lp[q] = lv;
+    for (int k = 0; k < kTaps; ++k) {
+      const int yi = along(y, -tap_offset(s, k), ny, a.per_y);
+      if (yi >= 0 && (a.per_y || (yi >= 1 && yi <= ny - 2)))
+        acc += WY[yi * kWeightsPerNode + s * kTaps + k] *
+               mu[q * plane + static_cast<long long>(yi) * a.pitch + c];
     }
-    load9(lamQ, a.plane, off, lq);
-    double rho, ux, uy;
-    node_rho_u(v, rho, ux, uy);
-    Real feq[kQ], mix[kQ];
-    feq_dev(rho - 1.0, rho, ux, uy, feq);
+    return acc;
+  };
+
+  const long long total = static_cast<long long>(nstrips) * ny;
+  long long beg = total * blockIdx.x / gridDim.x;
+  const long long end = total * (blockIdx.x + 1) / gridDim.x;
+  while (beg < end) {  // uniform per block
+    const int strip = static_cast<int>(beg / ny);
+    const int y0 = static_cast<int>(beg % ny);
+    const int y1 = static_cast<int>(min(static_cast<long long>(ny), y0 + (end - beg)));
+    beg += y1 - y0;
+    const int x0 = strip * kStripOut;
+    const int x1 = min(x0 + kStripOut, nx);
+    const int c0 = x0 - kHalo + lane;  // this lane's column, unwrapped
+    const bool in_x = a.per_x || (c0 >= 0 && c0 < nx);
+    const int c = a.per_x ? wrap(c0, nx) : clampi(c0, 0, nx - 1);
+    const bool col_int = in_x && (a.per_x || (c0 >= 1 && c0 <= nx - 2));
+    const bool lane_o = lane >= kHalo && lane < kLanes - kHalo && c0 < x1;
+    const bool xl = !a.per_x && c0 == 1, xr = !a.per_x && c0 == nx - 2;
+    Real wx[kWeightsPerNode];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q)
-      mix[q] = static_cast<Real>(a.cPe) * lp[q] + static_cast<Real>(a.cQe) * lq[q];
-    double fa, fbx, fby;
-    feq_ab(rho, ux, uy, mix, fa, fbx, fby);
-    Real out[kQ];
-    through_moments(rho, ux, uy, fa, fbx, fby, out, false);
+    for (int k = 0; k < kWeightsPerNode; ++k) wx[k] = in_x ? WX[c * kWeightsPerNode + k] : Real(0);
+    __syncthreads();  // ring zero-fill / previous piece complete
+
+    const int niter = (y1 - y0 + 7) / kRowsPerIter;
+    for (int it = 0; it < niter; ++it) {
+      const int p0 = y0 - 2 + kRowsPerIter * it;
+
+      // ---- phase A: lamS of row r
+      {
+        const int r0 = p0 + t;
+        const bool in_y = a.per_y || (r0 >= 0 && r0 < ny);
+        Real ls[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      out[q] += static_cast<Real>(a.cPg) * lp[q] + static_cast<Real>(a.cQg) * lq[q];
-      lam_out[q * a.plane + off] = out[q];
-      dw += (a.dcPg * static_cast<double>(lp[q]) + a.dcQg * static_cast<double>(lq[q])) *
-            static_cast<double>(v[q] - feq[q]);
+        for (int q = 0; q < kQ; ++q) ls[q] = Real(0);
+        if (in_y) {  // uniform per wave
+          const int r = a.per_y ? wrap(r0, ny) : r0;
+          const bool row_int = a.per_y || (r >= 1 && r <= ny - 2);
+          const bool nin = col_int && row_int;
+          const long long roff = static_cast<long long>(r) * a.pitch + c;
+          Real lr[kQ];
+          lr[0] = Real(0);
+#pragma unroll
+          for (int q = 1; q < kQ; ++q) {
+            // x part: sources (c - o_k, r), o_k the tap offset
+            Real acc = Real(0);
+            if (ex_of(q) != 0) {
+              const Real m = nin ? mu[q * plane + roff] : Real(0);
+              if (ex_of(q) > 0) {  // o = -2, -1, 0, +1
+                acc = from_above(from_above(wx[0] * m)) + from_above(wx[1] * m) + wx[2] * m +
+                      from_below(wx[3] * m);
+              } else {  // o = -1, 0, +1, +2
+                acc = from_above(wx[4] * m) + wx[5] * m + from_below(wx[6] * m) +
+                      from_below(from_below(wx[7] * m));
+              }
+            }
+            lr[q] = acc + (row_int ? lamR_y(q, c, col_int, r) : Real(0));
+          }
+          // lamR of the x-wall neighbour (its own lane computed it above)
+          Real lw[kQ];
+          lw[0] = Real(0);
+          if (!a.per_x) {
+#pragma unroll
+            for (int q = 1; q < kQ; ++q) {
+              const Real lo = from_below(lr[q]), hi = from_above(lr[q]);
+              lw[q] = xl ? lo : hi;
+            }
+          }
+          if (nin) {
+            Real sv[kQ];
+            load9(S, plane, roff, sv);
+            double rho, ux, uy;
+            node_rho_u(sv, rho, ux, uy);
+            auto add_wall = [&](int bx, int by, const Real lb[kQ]) {
+              double ub, vb;
+              wall_vel(a, bx, by, ub, vb);
+              double sa, sbx, sby;
+              shift_ab(rho, ux, uy, ub, vb, lb, sa, sbx, sby);
+#pragma unroll
+              for (int q = 0; q < kQ; ++q) lr[q] += lb[q];
+              through_moments(rho, ux, uy, sa, sbx, sby, ls, true);
+            };
+            if (xl) add_wall(0, r, lw);
+            if (xr) add_wall(nx - 1, r, lw);
+            if (!a.per_y && (r == 1 || r == ny - 2)) {
+              const int by = r == 1 ? 0 : ny - 1;
+              Real lb[kQ];
+              lb[0] = Real(0);
+#pragma unroll
+              for (int q = 1; q < kQ; ++q) lb[q] = lamR_y(q, c, col_int, by);
+              add_wall(c, by, lb);
+            }
+            Real feq[kQ];
+            feq_dev(rho - 1.0, rho, ux, uy, feq);
+            double fa, fbx, fby;
+            feq_ab(rho, ux, uy, lr, fa, fbx, fby);
+            Real jt[kQ];
+            const double cRe = a.cRe;
+            through_moments(rho, ux, uy, cRe * fa, cRe * fbx, cRe * fby, jt, false);
+            const bool own = lane_o && r0 >= y0 && r0 < y1;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+              ls[q] += static_cast<Real>(a.cRs) * lr[q] + jt[q];
+              if (own) dw += static_cast<double>(lr[q]) * a.dcRs * static_cast<double>(sv[q] - feq[q]);
+            }
+          }
+        }
+        Real* slot = ring + (r0 & (kRing - 1)) * kQ * kLanes;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) slot[q * kLanes + lane] = ls[q];
+      }
+      __syncthreads();
+
+      // ---- phase B: lam_n of row o
+      {
+        const int o = p0 - 2 + t;
+        if (o >= y0 && o < y1) {  // uniform per wave
+          const bool nin = col_int && (a.per_y || (o >= 1 && o <= ny - 2));
+          const Real* cen = ring + (o & (kRing - 1)) * kQ * kLanes + lane;
+          Real lp[kQ];
+#pragma unroll
+          for (int q = 0; q < kQ; ++q) {
+            const Real l = cen[q * kLanes];
+            Real acc = Real(0);
+            if (ex_of(q) > 0)
+              acc = from_above(from_above(wx[0] * l)) + from_above(wx[1] * l) + wx[2] * l +
+                    from_below(wx[3] * l);
+            if (ex_of(q) < 0)
+              acc = from_above(wx[4] * l) + wx[5] * l + from_below(wx[6] * l) +
+                    from_below(from_below(wx[7] * l));
+            if (ey_of(q) != 0) {
+              const int s = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+              for (int k = 0; k < kTaps; ++k) {
+                const int yu = o - tap_offset(s, k);  // unwrapped source row
+                const int yi = along(o, -tap_offset(s, k), ny, a.per_y);
+                if (yi >= 0)
+                  acc += WY[yi * kWeightsPerNode + s * kTaps + k] *
+                         ring[(yu & (kRing - 1)) * kQ * kLanes + q * kLanes + lane];
+              }
+            }
+            lp[q] = (nin ? l : Real(0)) + (q == 0 ? Real(0) : A * acc);
+          }
+          const long long ooff = static_cast<long long>(o) * a.pitch + c;
+          Real v[kQ], lq[kQ];
+#pragma unroll
+          for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * plane + ooff]);
+          load9(mu, plane, ooff, lq);
+          double rho, ux, uy;
+          node_rho_u(v, rho, ux, uy);
+          Real feq[kQ], mix[kQ];
+          feq_dev(rho - 1.0, rho, ux, uy, feq);
+#pragma unroll
+          for (int q = 0; q < kQ; ++q)
+            mix[q] = static_cast<Real>(a.cPe) * lp[q] + static_cast<Real>(a.cQe) * lq[q];
+          double fa, fbx, fby;
+          feq_ab(rho, ux, uy, mix, fa, fbx, fby);
+          Real out[kQ];
+          through_moments(rho, ux, uy, fa, fbx, fby, out, false);
+#pragma unroll
+          for (int q = 0; q < kQ; ++q) {
+            out[q] += static_cast<Real>(a.cPg) * lp[q] + static_cast<Real>(a.cQg) * lq[q];
+            if (lane_o) {
+              lam_out[q * plane + ooff] = out[q];
+              dw += (a.dcPg * static_cast<double>(lp[q]) + a.dcQg * static_cast<double>(lq[q])) *
+                    static_cast<double>(v[q] - feq[q]);
+            }
+          }
+        }
+      }
+      __syncthreads();
     }
   }
   red[threadIdx.x] = dw;
@@ -457,10 +537,10 @@ hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp,
                        static_cast<const Store*>(a.next), mu);
     mu = static_cast<const Real*>(a.mu);
   }
-  hipLaunchKernelGGL(adj_S<Real>, dim3(G), dim3(256), 0, s, a, mu, partial);
-  hipLaunchKernelGGL(adj_g<Store>, dim3(G), dim3(256), 0, s, a, g, mu, static_cast<Real*>(lam_n),
-                     partial + G);
-  if (accum) hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, 2 * G, accum);
+  const int nstrips = (a.nx + kStripOut - 1) / kStripOut;
+  hipLaunchKernelGGL(adj_strip<Store>, dim3(G), dim3(256), 0, s, a, g, mu,
+                     static_cast<Real*>(lam_n), partial, nstrips);
+  if (accum) hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, G, accum);
   return hipGetLastError();
 }
 

@@ -554,8 +554,8 @@ size_t t2s2_adjoint_state_bytes(const t2s2_ctx* c) {
 
 size_t t2s2_adjoint_scratch_bytes(const t2s2_ctx* c) {
   if (!c) return 0;
-  return 3 * align256(t2s2_adjoint_state_bytes(c)) + align256(t2s2_state_bytes(c)) +
-         align256(2 * kDiagBlocks * sizeof(double));
+  return 2 * align256(t2s2_adjoint_state_bytes(c)) + align256(t2s2_state_bytes(c)) +
+         align256(kDiagBlocks * sizeof(double));
 }
 
 int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
@@ -598,9 +598,8 @@ int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
   const size_t ab = align256(t2s2_adjoint_state_bytes(c));
   a.S = p;
   a.mu = p + ab;
-  a.lamS = p + 2 * ab;
-  a.next = p + 3 * ab;
-  c->adj_partial = reinterpret_cast<double*>(p + 3 * ab + align256(t2s2_state_bytes(c)));
+  a.next = p + 2 * ab;
+  c->adj_partial = reinterpret_cast<double*>(p + 2 * ab + align256(t2s2_state_bytes(c)));
   c->adj_bound = true;
   return T2S2_OK;
 }

@@ -116,7 +116,6 @@ struct AdjParams {
   double uw[4][2];
   void* S;     // S, from the recompute of the step
   void* mu;    // adjoint of the interior output (= adjoint of Q); walled domains
-  void* lamS;  // adjoint of S
   void* next;  // f~^{n+1} recomputed (storage type)
 };
 

@@ -58,21 +58,6 @@ __device__ inline void row_weights(const Real* table, int row, Real out[kWeights
   for (int k = 0; k < kWeightsPerNode; ++k) out[k] = w[k];
 }
 
-// Value of the neighbouring lane l-1 (from_below) or l+1 (from_above) of a
-// wave64, through DPP wave shifts (two 32-bit moves for a double).  Every
-// lane of the wave must hold a defined value.  bound_ctrl makes the edge
-// lane (no source lane) read 0, so the move does not depend on the old
-// destination value and needs no zero-fill before it.
-__device__ inline int dpp_shr1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
-__device__ inline int dpp_shl1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
-__device__ inline double from_below(double v) {
-  return __hiloint2double(dpp_shr1(__double2hiint(v)), dpp_shr1(__double2loint(v)));
-}
-__device__ inline double from_above(double v) {
-  return __hiloint2double(dpp_shl1(__double2hiint(v)), dpp_shl1(__double2loint(v)));
-}
-__device__ inline float from_below(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
-__device__ inline float from_above(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
 
 // Element at a 32-bit byte offset from a plane base: the row offset is
 // formed once per row in 32 bits and shared by the nine planes.  Every
