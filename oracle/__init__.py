@@ -47,6 +47,8 @@ def _load():
         d, i, l, p = ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_void_p
         lib.oracle_run.argtypes = [i, i, p, p, i, i, d, d, d, d, d, d, d, d, p, d, i, p, l]
         lib.oracle_run.restype = i
+        lib.oracle_run_family.argtypes = [i, i, p, p, i, i, d, d, d, d, d, d, d, d, p, d, p, p, l]
+        lib.oracle_run_family.restype = i
         lib.oracle_init.argtypes = [i, i, p, p, p, p, d, d, d, p]
         lib.oracle_init.restype = i
         lib.oracle_moments.argtypes = [i, i, p, d, d, d, d, p, p, p]
@@ -122,11 +124,12 @@ def init(case, offset: float = 1.0, noneq: bool = True) -> np.ndarray:
 
 def run(case, phi: np.ndarray, nsteps: int, *, offset: float = 1.0, scheme: int = 1,
         A: float | None = None, eta: float | None = None, dt: float | None = None,
-        threads: int | None = None) -> np.ndarray:
+        threads: int | None = None, btilde=None) -> np.ndarray:
     """Advance a copy of phi by nsteps; returns the new state.
 
     scheme 1: T2S2-FDLBM1 family with h = A dt (A = 0.5 default, A = 0 is
-    Guo's T1S2); scheme 2: T2S2-FDLBM2."""
+    Guo's T1S2); scheme 2: T2S2-FDLBM2; scheme 3: the eq 2.13 family with
+    gradient weights btilde = (B~0, B~1, B~2) on L(f^n), L(f*), L(f^{n+1})."""
     lib = _load()
     if threads is None:
         # small grids: thread start-up costs more than the stage loops
@@ -137,13 +140,16 @@ def run(case, phi: np.ndarray, nsteps: int, *, offset: float = 1.0, scheme: int 
     x = np.ascontiguousarray(case.x, dtype=np.float64)
     y = np.ascontiguousarray(case.y, dtype=np.float64)
     uw = np.ascontiguousarray(case.u_wall, dtype=np.float64).reshape(8)
-    rc = lib.oracle_run(case.nx, case.ny, _ptr(x), _ptr(y), int(case.periodic_x),
-                        int(case.periodic_y), float(case.period_x), float(case.period_y),
-                        float(dt if dt is not None else time_step(case)), inv_tau(case),
-                        float(case.A if A is None else A),
-                        float(case.eta if eta is None else eta),
-                        float(case.force[0]), float(case.force[1]), _ptr(uw),
-                        float(offset), int(scheme), _ptr(out), int(nsteps))
+    args = (case.nx, case.ny, _ptr(x), _ptr(y), int(case.periodic_x),
+            int(case.periodic_y), float(case.period_x), float(case.period_y),
+            float(dt if dt is not None else time_step(case)), inv_tau(case),
+            float(case.A if A is None else A), float(case.eta if eta is None else eta),
+            float(case.force[0]), float(case.force[1]), _ptr(uw), float(offset))
+    if scheme == 3:
+        bt = np.ascontiguousarray(btilde, dtype=np.float64).reshape(3)
+        rc = lib.oracle_run_family(*args, _ptr(bt), _ptr(out), int(nsteps))
+    else:
+        rc = lib.oracle_run(*args, int(scheme), _ptr(out), int(nsteps))
     if rc != 0:
         raise ValueError(f"oracle_run failed ({rc})")
     return out

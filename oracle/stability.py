@@ -9,11 +9,13 @@ equilibrium f^eq(rho = 1, u) (eq 4.4) is built two ways:
 
 * ``paper``: eq 4.7 for the (B~2, B-2) family with the eq 4.8 symbol S of
   the mixed difference;
-* ``fdlbm1`` / ``fdlbm2``: the exact linearisation of the implemented steps
-  (the eq 2.23 march with h = A dt, and the eq 5.23 march), composed from
-  the Jacobians of the pointwise maps and the difference symbol:
+* ``fdlbm1`` / ``fdlbm2`` / ``family``: the exact linearisation of the
+  implemented steps (the eq 2.23 march with h = A dt, the eq 5.23 march, and
+  the eq 2.13 family with gradient weights B~), composed from the Jacobians
+  of the pointwise maps and the difference symbol:
       fdlbm1:  G = J_Q - rS J_R (I - A rS) J_P
       fdlbm2:  G = J_Q - (rS / 2) [J_f + J_R1 (I - rS) J_Q]
+      family:  G = J_Q - rS [B~0 J_f + B~1 J_R (I - A rS) J_P + B~2 J_R1 (I - rS) J_Q]
   with J_X = c_Xg I + c_Xe Gamma (the coefficients of the P, Q, R maps).
 
 Readings (listed in the design notes):
@@ -109,13 +111,33 @@ def growth_fdlbm2(theta_x, theta_y, omega, r, eta, u):
     return JQ - 0.5 * rS @ (Jf + JR @ (I - rS) @ JQ)
 
 
-def growth(model, theta_x, theta_y, omega, r, *, eta, u, A=0.5, B2bar=0.5, B2tilde=0.0):
+def growth_family(theta_x, theta_y, omega, r, A, btilde, eta, u):
+    """Exact linearisation of the eq 2.13 family step with Bbar = (1/2, 0,
+    1/2) and gradient weights btilde on L(f^n), L(f*), L(f^{n+1}):
+        G = J_Q - rS [B~0 J_f + B~1 J_R(A) (I - A rS) J_P + B~2 J_R(1) (I - rS) J_Q]."""
+    I = np.eye(9)
+    G = gamma(u)
+    c, c0, c1 = coefficients(A, omega), coefficients(0.0, omega), coefficients(1.0, omega)
+    JP = c["cPg"] * I + c["cPe"] * G
+    JQ = c["cQg"] * I + c["cQe"] * G
+    JR = c["cRs"] * I + c["cRe"] * G
+    Jf = c0["cPg"] * I + c0["cPe"] * G
+    JR1 = c1["cRs"] * I + c1["cRe"] * G
+    rS = r * np.diag(symbol(theta_x, theta_y, eta))
+    b0, b1, b2 = btilde
+    return JQ - rS @ (b0 * Jf + b1 * JR @ (I - A * rS) @ JP + b2 * JR1 @ (I - rS) @ JQ)
+
+
+def growth(model, theta_x, theta_y, omega, r, *, eta, u, A=0.5, B2bar=0.5, B2tilde=0.0,
+           btilde=(0.0, 1.0, 0.0)):
     if model == "paper":
         return growth_paper(theta_x, theta_y, omega, r, B2bar, B2tilde, eta, u)
     if model == "fdlbm1":
         return growth_fdlbm1(theta_x, theta_y, omega, r, A, eta, u)
     if model == "fdlbm2":
         return growth_fdlbm2(theta_x, theta_y, omega, r, eta, u)
+    if model == "family":
+        return growth_family(theta_x, theta_y, omega, r, A, btilde, eta, u)
     raise ValueError(model)
 
 

@@ -22,7 +22,8 @@
  * BGK collision (eq 2.4), the equilibrium of eq 3.2, moments of eq 3.3,
  * Guo's force term of eq 3.12 and the mixed central / second-order upwind
  * difference of eqs 2.36-2.38.  Wall nodes use non-equilibrium extrapolation
- * (eq 3.10).  The T2S2-FDLBM2 sequence (eq 5.23, Sec. 2D) is scheme 2.
+ * (eq 3.10).  The T2S2-FDLBM2 sequence (eq 5.23, Sec. 2D) is scheme 2; the
+ * eq 2.13 family with general gradient weights B~ is step_family.
  *
  * Readings where the paper is silent or garbled (each one is listed with its
  * justification in the design notes of the repository):
@@ -346,18 +347,58 @@ static void step_fdlbm2(const grid_t* g, double* ft, double* Fn, double* Qp, dou
   nee_walls(g, out, dt / 2.0);
 }
 
+/* The eq 2.13 family with the collision weights of eqs 2.21 and 5.21,
+ * Bbar = (1/2, 0, 1/2), and gradient weights bt = (B~0, B~1, B~2):
+ *   f~^{n+1} = f~^{+,n} + dt [B~0 L(f^n) + B~1 L(f*) + B~2 L(f^{n+1})]
+ * (eq 2.13 under the transform of eqs 2.19-2.20).  Each argument of L is
+ * the paper's own prediction of it: f* by step (1) of the T2S2-FDLBM1
+ * sequence (h = A dt), f^{n+1} by step (2) of the T2S2-FDLBM2 sequence
+ * (h = dt), f^n by eq 2.52 at h = 0 (step (1) of the second sequence).
+ * bt = (0, 1, 0) is eq 2.23, (1/2, 0, 1/2) eq 5.23 and (1, 0, 0) eq 2.18. */
+static void step_family(const grid_t* g, const double bt[3], double* ft, double* P, double* Fn,
+                        double* Qp, double* S, double* R1, double* R2) {
+  const double h = g->A * g->dt, dt = g->dt;
+  size_t n = (size_t)Q * g->nx * g->ny;
+  collide_all(g, ft, h, P, Qp);      /* P = fbar^{+,h}(t_n), Qp = f~^{+,n} */
+  collide_all(g, ft, 0.0, Fn, NULL); /* f^n */
+  /* f(t*) from P along the characteristics, h = A dt */
+  memcpy(S, P, n * sizeof(double));
+  advect_interior(g, P, h, S);
+  memcpy(R1, S, n * sizeof(double));
+  unshift_interior(g, S, h, R1);
+  nee_walls(g, R1, 0.0);
+  /* f(t_{n+1}) from f~^+ along the characteristics, h = dt */
+  memcpy(S, Qp, n * sizeof(double));
+  advect_interior(g, Qp, dt, S);
+  memcpy(R2, S, n * sizeof(double));
+  unshift_interior(g, S, dt, R2);
+  nee_walls(g, R2, 0.0);
+  memcpy(ft, Qp, n * sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < g->ny; ++j)
+    for (int i = 0; i < g->nx; ++i) {
+      if (is_wall(g, i, j)) continue;
+      for (int q = 0; q < Q; ++q) {
+        double l = bt[0] * L_term(g, Fn, q, i, j) + bt[1] * L_term(g, R1, q, i, j) +
+                   bt[2] * L_term(g, R2, q, i, j);
+        ft[IDX(g, q, i, j)] = Qp[IDX(g, q, i, j)] + dt * l;
+      }
+    }
+  nee_walls(g, ft, dt / 2.0);
+}
+
 /* ------------------------------------------------------------ public API */
 
 /* Advance phi (= f~ - offset*w, layout [9][ny][nx]) by nsteps.
  * nu_inv_tau: 1/tau (0 = collisionless).  u_wall: [4][2] left,right,bottom,top.
  * scheme: 1 = T2S2-FDLBM1 family (A selects h = A dt), 2 = T2S2-FDLBM2.
  * Returns 0 on success, 1 on bad arguments, 2 on allocation failure. */
-int oracle_run(int nx, int ny, const double* x, const double* y, int per_x, int per_y,
-               double period_x, double period_y, double dt, double inv_tau, double A,
-               double eta, double Fx, double Fy, const double* u_wall, double offset,
-               int scheme, double* phi, long nsteps) {
+static int run_impl(int nx, int ny, const double* x, const double* y, int per_x, int per_y,
+                    double period_x, double period_y, double dt, double inv_tau, double A,
+                    double eta, double Fx, double Fy, const double* u_wall, double offset,
+                    int scheme, const double* bt, double* phi, long nsteps) {
   if (nx < 5 || ny < 5 || dt <= 0.0 || inv_tau < 0.0 || !phi || !x || !y) return 1;
-  if (scheme != 1 && scheme != 2) return 1;
+  if (scheme != 1 && scheme != 2 && !(scheme == 3 && bt)) return 1;
   grid_t g;
   memset(&g, 0, sizeof g);
   g.nx = nx;
@@ -383,8 +424,10 @@ int oracle_run(int nx, int ny, const double* x, const double* y, int per_x, int 
   double* Qp = (double*)malloc(n * sizeof(double));
   double* S = (double*)malloc(n * sizeof(double));
   double* R = (double*)malloc(n * sizeof(double));
+  double* Fn = scheme == 3 ? (double*)malloc(n * sizeof(double)) : NULL;
+  double* R2 = scheme == 3 ? (double*)malloc(n * sizeof(double)) : NULL;
   int rc = 0;
-  if (!g.mx || !g.my || !P || !Qp || !S || !R) {
+  if (!g.mx || !g.my || !P || !Qp || !S || !R || (scheme == 3 && (!Fn || !R2))) {
     rc = 2;
   } else {
     metric(nx, x, per_x, period_x, g.mx);
@@ -392,8 +435,10 @@ int oracle_run(int nx, int ny, const double* x, const double* y, int per_x, int 
     for (long s = 0; s < nsteps; ++s) {
       if (scheme == 1)
         step_fdlbm1(&g, phi, P, Qp, S, R);
-      else
+      else if (scheme == 2)
         step_fdlbm2(&g, phi, P, Qp, S, R);
+      else
+        step_family(&g, bt, phi, P, Fn, Qp, S, R, R2);
     }
   }
   free(g.mx);
@@ -402,7 +447,28 @@ int oracle_run(int nx, int ny, const double* x, const double* y, int per_x, int 
   free(Qp);
   free(S);
   free(R);
+  free(Fn);
+  free(R2);
   return rc;
+}
+
+int oracle_run(int nx, int ny, const double* x, const double* y, int per_x, int per_y,
+               double period_x, double period_y, double dt, double inv_tau, double A,
+               double eta, double Fx, double Fy, const double* u_wall, double offset,
+               int scheme, double* phi, long nsteps) {
+  if (scheme != 1 && scheme != 2) return 1;
+  return run_impl(nx, ny, x, y, per_x, per_y, period_x, period_y, dt, inv_tau, A, eta, Fx, Fy,
+                  u_wall, offset, scheme, NULL, phi, nsteps);
+}
+
+/* The eq 2.13 family (step_family) with gradient weights bt[3]. */
+int oracle_run_family(int nx, int ny, const double* x, const double* y, int per_x, int per_y,
+                      double period_x, double period_y, double dt, double inv_tau, double A,
+                      double eta, double Fx, double Fy, const double* u_wall, double offset,
+                      const double* bt, double* phi, long nsteps) {
+  if (!bt) return 1;
+  return run_impl(nx, ny, x, y, per_x, per_y, period_x, period_y, dt, inv_tau, A, eta, Fx, Fy,
+                  u_wall, offset, 3, bt, phi, nsteps);
 }
 
 /* Initial populations (Sec. 3): f~ = f^eq(rho, u), optionally minus the

@@ -273,7 +273,7 @@ def test_A_half_differs_from_t1s2():
 def test_temporal_order_by_step_halving(A, lo, hi):
     """At a fixed mesh, velocity differences between dt, dt/2, dt/4 runs to
     the same final time shrink as dt^2 for T2S2-FDLBM1 and as dt for T1S2
-    (Sec. 3B, Table 6; P:1026-1030 of the conclusions on temporal order)."""
+    (Sec. 3B, Table 6, and the temporal-order statement of Sec. 4)."""
     us = []
     for k in range(3):
         n = 400 * 2 ** k
