@@ -162,6 +162,20 @@ int t2s2_read_distributions(t2s2_ctx* ctx, double* g);
  * out[3] > 0. */
 int t2s2_diagnostics(t2s2_ctx* ctx, double out[T2S2_NDIAG]);
 
+/* Sums for the global relative error of the velocity (eq 3.6) against a
+ * reference field u' = (ux_ref, uy_ref): device FP64 arrays [ny][nx]
+ * (row-major, no pitch), read only.  out (host) receives
+ *   out[0] = sum |u - u'|^2,  out[1] = sum |u'|^2,  out[2] = sum |u|^2
+ * over all nodes of the current state, u the velocity of the moments
+ * (t2s2_moments).  E(u) of eq 3.6 is sqrt(out[0] / out[1]) for an analytic
+ * u'; the residual GRE of the cavity (Sec. 3C) is sqrt(out[0] / out[2])
+ * with u' the velocity at the previous output time.  Deterministic
+ * reduction; synchronises.  Non-finite populations make the sums
+ * non-finite (no error code; t2s2_diagnostics counts them).  Errors:
+ * INVALID_ARG (NULL pointer), NOT_BOUND, HIP_ERROR. */
+int t2s2_velocity_error(t2s2_ctx* ctx, const double* ux_ref, const double* uy_ref,
+                        double out[3]);
+
 /* Relaxation parameter omega = dt / tau in use (0 without collision). */
 double t2s2_omega(const t2s2_ctx* ctx);
 

@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
         "t2s2_moments": (i, [vp, vp, vp, vp]),
         "t2s2_read_distributions": (i, [vp, vp]),
         "t2s2_diagnostics": (i, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "t2s2_velocity_error": (i, [vp, vp, vp, ctypes.POINTER(ctypes.c_double)]),
         "t2s2_omega": (d, [vp]),
         "t2s2_adjoint_state_bytes": (sz, [vp]),
         "t2s2_adjoint_scratch_bytes": (sz, [vp]),
@@ -129,7 +130,7 @@ def exported_symbols() -> Sequence[str]:
             "t2s2_init_macro", "t2s2_init_distributions", "t2s2_step", "t2s2_graph_capture",
             "t2s2_graph_step", "t2s2_current",
             "t2s2_steps_taken", "t2s2_dt", "t2s2_moments", "t2s2_read_distributions",
-            "t2s2_diagnostics", "t2s2_omega", "t2s2_adjoint_state_bytes",
+            "t2s2_diagnostics", "t2s2_velocity_error", "t2s2_omega", "t2s2_adjoint_state_bytes",
             "t2s2_adjoint_scratch_bytes", "t2s2_bind_adjoint", "t2s2_adjoint_seed_velocity",
             "t2s2_adjoint_step", "t2s2_adjoint_init_macro", "t2s2_adjoint_read",
             "t2s2_adjoint_load", "t2s2_stability_map", "t2s2_destroy", "t2s2_last_error")
@@ -261,6 +262,24 @@ class Context:
         out = [t.empty((self.ny, self.nx), dtype=t.float64, device=self.device) for _ in range(3)]
         _check(_lib.t2s2_moments(self._h, *[o.data_ptr() for o in out]))
         return tuple(out)
+
+    def velocity_error(self, ux_ref, uy_ref) -> dict:
+        """Global relative error of the velocity against a reference field
+        (t2s2_velocity_error): ``gre`` = E(u) of eq 3.6 (normalised by the
+        reference), ``residual`` = the Sec. 3C form (normalised by the
+        current field; pass the previous output's velocity), and the sums."""
+        t = self._torch
+        refs = [t.as_tensor(r, dtype=t.float64, device=self.device).contiguous()
+                for r in (ux_ref, uy_ref)]
+        for r in refs:
+            if tuple(r.shape) != (self.ny, self.nx):
+                raise ValueError(f"reference field must be ({self.ny}, {self.nx})")
+        out = (ctypes.c_double * 3)()
+        _check(_lib.t2s2_velocity_error(self._h, refs[0].data_ptr(), refs[1].data_ptr(), out))
+        d2, r2, u2 = list(out)
+        return {"gre": (d2 / r2) ** 0.5 if r2 > 0 else float("nan"),
+                "residual": (d2 / u2) ** 0.5 if u2 > 0 else float("nan"),
+                "sum_diff2": d2, "sum_ref2": r2, "sum_u2": u2}
 
     def read_distributions(self):
         t = self._torch

@@ -545,6 +545,28 @@ int t2s2_diagnostics(t2s2_ctx* c, double out[T2S2_NDIAG]) {
   return T2S2_OK;
 }
 
+int t2s2_velocity_error(t2s2_ctx* c, const double* ux_ref, const double* uy_ref,
+                        double out[3]) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (!ux_ref || !uy_ref || !out) return fail(T2S2_ERR_INVALID_ARG, "NULL reference or output");
+  double* part = reinterpret_cast<double*>(c->ws + c->off_part);
+  double* res = reinterpret_cast<double*>(c->ws + c->off_res);
+  hipError_t e = launch_velocity_error(c->cfg.storage, c->ap, c->state[c->cur], ux_ref, uy_ref,
+                                       part, res, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "velocity_error");
+  double host[kDiagSlots];
+  e = hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "velocity_error: copy");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "velocity_error: synchronize");
+  out[0] = host[0];
+  out[1] = host[1];
+  out[2] = host[3];
+  return T2S2_OK;
+}
+
 double t2s2_omega(const t2s2_ctx* c) { return c ? c->omega : 0.0; }
 
 size_t t2s2_adjoint_state_bytes(const t2s2_ctx* c) {

@@ -138,6 +138,9 @@ hipError_t launch_moments(int storage, const AuxParams& a, const void* state, do
                           double* ux, double* uy, hipStream_t s);
 hipError_t launch_diagnostics(int storage, const AuxParams& a, const void* state,
                               double* partials, double* result, hipStream_t s);
+hipError_t launch_velocity_error(int storage, const AuxParams& a, const void* state,
+                                 const double* uref, const double* vref, double* partials,
+                                 double* result, hipStream_t s);
 
 size_t storage_bytes(int storage);
 

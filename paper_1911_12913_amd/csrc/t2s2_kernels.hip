@@ -638,6 +638,47 @@ __global__ __launch_bounds__(64) void diag_final_kernel(const double* partials, 
   }
 }
 
+// Sums for the global relative error of the velocity against a reference
+// field (eq 3.6, and the residual form of Sec. 3C): slot 0 sum |u - u'|^2,
+// slot 1 sum |u'|^2, slot 3 sum |u|^2, over all nodes, the other slots
+// zero (slot 2 is a max in the final pass).  Same fixed partition and order
+// as the diagnostics.
+template <typename Store>
+__global__ __launch_bounds__(256) void gre_partial_kernel(AuxParams a, const Store* state,
+                                                          const double* uref,
+                                                          const double* vref,
+                                                          double* partials) {
+  __shared__ double red[3][256];
+  double acc[3] = {0.0, 0.0, 0.0};
+  const long long n = static_cast<long long>(a.nx) * a.ny;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    const int x = static_cast<int>(i % a.nx), y = static_cast<int>(i / a.nx);
+    double s, u, v;
+    bool fin;
+    node_moments(a, state, x, y, s, u, v, fin);
+    const double ur = uref[i], vr = vref[i];
+    const double du = u - ur, dv = v - vr;
+    acc[0] += du * du + dv * dv;
+    acc[1] += ur * ur + vr * vr;
+    acc[2] += u * u + v * v;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kDiagSlots) {
+    const int k = threadIdx.x;
+    partials[blockIdx.x * kDiagSlots + k] =
+        k == 0 ? red[0][0] : (k == 1 ? red[1][0] : (k == 3 ? red[2][0] : 0.0));
+  }
+}
+
 template <typename Store, int kScheme>
 void launch_fused(const StepParams& p, dim3 g, dim3 b, hipStream_t s, bool walls) {
   if (p.has_force) {
@@ -791,6 +832,18 @@ hipError_t launch_diagnostics(int storage, const AuxParams& a, const void* state
   T2S2_DISPATCH(storage,
                 hipLaunchKernelGGL(diag_partial_kernel<Store>, dim3(kDiagBlocks), dim3(256), 0,
                                    s, a, static_cast<const Store*>(state), partials));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, kDiagBlocks, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_velocity_error(int storage, const AuxParams& a, const void* state,
+                                 const double* uref, const double* vref, double* partials,
+                                 double* result, hipStream_t s) {
+  T2S2_DISPATCH(storage,
+                hipLaunchKernelGGL(gre_partial_kernel<Store>, dim3(kDiagBlocks), dim3(256), 0,
+                                   s, a, static_cast<const Store*>(state), uref, vref, partials));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, kDiagBlocks, result);

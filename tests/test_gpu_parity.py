@@ -205,6 +205,40 @@ def test_nonfinite_state_is_reported():
     assert ctx.diagnostics(raise_nonfinite=False)["nonfinite"] == 1
 
 
+def test_velocity_error_eq36_and_residual():
+    """t2s2_velocity_error: E(u) of eq 3.6 against the Taylor-Green closed
+    form (eq 3.4) and the residual GRE of the cavity (Sec. 3C).  The sums
+    equal host sums over the GPU's own moments; E(u) equals the oracle's at
+    the same step; repeated calls give the same bits."""
+    case = W.tgv_case(64, 48, u0=0.05, nu=0.01, cfl=0.5, eta=0.01)
+    phi0 = oracle.init(case)
+    n = 200
+    ctx, g, d, u, v = _gpu_run(case, phi0, n)
+    t = n * oracle.time_step(case)
+    _, ue, ve, _ = W.tgv_fields(case.x, case.y, 1.0, 1.0, 0.05, case.nu, t)
+    r = ctx.velocity_error(torch.from_numpy(ue), torch.from_numpy(ve))
+    assert r["sum_diff2"] == pytest.approx(np.sum((u - ue) ** 2 + (v - ve) ** 2), rel=1e-12)
+    assert r["sum_ref2"] == pytest.approx(np.sum(ue ** 2 + ve ** 2), rel=1e-13)
+    assert r["sum_u2"] == pytest.approx(np.sum(u ** 2 + v ** 2), rel=1e-13)
+    _, uo, vo = oracle.moments(case, oracle.run(case, phi0, n))
+    e_oracle = math.sqrt(np.sum((uo - ue) ** 2 + (vo - ve) ** 2) / np.sum(ue ** 2 + ve ** 2))
+    print(f"    tgv64x48 E(u) at t = {t:.4f}: gpu {r['gre']:.10e} oracle {e_oracle:.10e}",
+          flush=True)
+    assert r["gre"] == pytest.approx(e_oracle, rel=1e-8)
+    assert ctx.velocity_error(torch.from_numpy(ue), torch.from_numpy(ve)) == r
+    with pytest.raises(ValueError):
+        ctx.velocity_error(np.zeros((48, 63)), np.zeros((48, 64)))
+
+    cav = W.cavity_case(64, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
+    c2, _, _, up, vp = _gpu_run(cav, oracle.init(cav), 100)
+    c2.step(1)
+    _, un, vn = (a.cpu().numpy() for a in c2.moments())
+    r = c2.velocity_error(torch.from_numpy(up), torch.from_numpy(vp))
+    res = math.sqrt(np.sum((un - up) ** 2 + (vn - vp) ** 2) / np.sum(un ** 2 + vn ** 2))
+    print(f"    cavity65 residual GRE after 101 steps: {r['residual']:.6e}", flush=True)
+    assert r["residual"] == pytest.approx(res, rel=1e-10)
+
+
 @pytest.mark.parametrize("storage,tol", [("f32", 3e-5), ("f16", 5e-2), ("bf16", 0.6)])
 def test_reduced_precision_error_vs_oracle(storage, tol):
     """Deviation storage in FP32 / FP16 / BF16 with FP32 arithmetic and FP64
