@@ -56,9 +56,16 @@ extern "C" {
 /* Time-marching scheme (Sec. 2A, Sec. 2D).  T2S2_FDLBM1: eq 2.23, the
  * intermediate stage at t + A dt (A = 1/2: T2S2-FDLBM1, A = 0: T1S2).
  * T2S2_FDLBM2: eq 5.23, f~^{n+1} = f~^{+,n} + dt/2 (L(f^n) + L(f^{n+1})) with
- * f^{n+1} predicted by a full-step characteristic update; A is not used. */
+ * f^{n+1} predicted by a full-step characteristic update; A is not used.
+ * T2S2_FAMILY: the eq 2.13 family with the collision weights of eqs 2.21
+ * and 5.21 (Bbar = (1/2, 0, 1/2)) and gradient weights btilde:
+ *   f~^{n+1} = f~^{+,n} + dt [B~0 L(f^n) + B~1 L(f*) + B~2 L(f^{n+1})],
+ * f* predicted as in T2S2_FDLBM1 (h = A dt) and f^{n+1} as in T2S2_FDLBM2.
+ * btilde = (0, 1, 0) is T2S2_FDLBM1 and (1/2, 0, 1/2) T2S2_FDLBM2;
+ * A B~1 + B~2 = 1/2 gives second order in time (eq 2.14b). */
 #define T2S2_FDLBM1 1
 #define T2S2_FDLBM2 2
+#define T2S2_FAMILY 3
 
 /* Number of values written by t2s2_diagnostics. */
 #define T2S2_NDIAG 6
@@ -77,7 +84,11 @@ typedef struct t2s2_config {
   double period_x;
   double period_y;
   int storage;          /* T2S2_F64, T2S2_F32_DEV, T2S2_BF16_DEV, T2S2_F16_DEV */
-  int scheme;           /* T2S2_FDLBM1 (0 is read as this) or T2S2_FDLBM2 */
+  int scheme;           /* T2S2_FDLBM1 (0 is read as this), T2S2_FDLBM2 or
+                           T2S2_FAMILY */
+  double btilde[3];     /* T2S2_FAMILY only: (B~0, B~1, B~2), each >= 0,
+                           B~0, B~1 <= 1, B~2 <= 1/2, summing to 1 within
+                           1e-12 (eq 2.14a); ignored by the other schemes */
 } t2s2_config;
 
 typedef struct t2s2_ctx t2s2_ctx;
@@ -231,7 +242,9 @@ int t2s2_adjoint_load(t2s2_ctx* ctx, const double* in, void* lam);
  *                    the advection symbol applied from the left;
  *   T2S2_STAB_FDLBM1 the exact linearisation of the step of eq 2.23 with
  *                    h = A dt (the step t2s2_step takes for T2S2_FDLBM1);
- *   T2S2_STAB_FDLBM2 the exact linearisation of the eq 5.23 step.
+ *   T2S2_STAB_FDLBM2 the exact linearisation of the eq 5.23 step;
+ *   T2S2_STAB_FAMILY the exact linearisation of the T2S2_FAMILY step with
+ *                    gradient weights btilde and h = A dt.
  * S is the symbol of the mixed difference (eq 4.8 with the imaginary unit
  * in its exponentials).  Modes: theta_y = k_y dx in [0, pi] (nk points);
  * theta_x in [0, pi] (nk points) or, with full_kx, in [-pi, pi] (2 nk - 1
@@ -242,17 +255,20 @@ int t2s2_adjoint_load(t2s2_ctx* ctx, const double* in, void* lam);
 #define T2S2_STAB_PAPER 0
 #define T2S2_STAB_FDLBM1 1
 #define T2S2_STAB_FDLBM2 2
+#define T2S2_STAB_FAMILY 3
 
 typedef struct t2s2_stability_params {
-  int model;       /* T2S2_STAB_PAPER, T2S2_STAB_FDLBM1, T2S2_STAB_FDLBM2 */
+  int model;       /* T2S2_STAB_PAPER, _FDLBM1, _FDLBM2 or _FAMILY */
   double eta;      /* upwind weight, in [0, 1] */
-  double A;        /* intermediate stage (T2S2_STAB_FDLBM1), in [0, 1] */
+  double A;        /* intermediate stage (_FDLBM1, _FAMILY), in [0, 1] */
   double b2bar;    /* B-2 of eq 4.7 (T2S2_STAB_PAPER) */
   double b2tilde;  /* B~2 of eq 4.7 (T2S2_STAB_PAPER) */
   double u[2];     /* velocity of the uniform state */
   int nk;          /* modes per half axis, 2..257 */
   int full_kx;     /* 1: theta_x in [-pi, pi]; 0: [0, pi] */
   int squarings;   /* 1..60 */
+  double btilde[3]; /* T2S2_STAB_FAMILY: (B~0, B~1, B~2), finite (any
+                       weights; the step's own ranges are not imposed) */
 } t2s2_stability_params;
 
 int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, const double* r,

@@ -47,6 +47,7 @@ class Config(ctypes.Structure):
         ("period_y", ctypes.c_double),
         ("storage", ctypes.c_int),
         ("scheme", ctypes.c_int),
+        ("btilde", ctypes.c_double * 3),
     ]
 
 
@@ -63,10 +64,11 @@ class StabilityParams(ctypes.Structure):
         ("nk", ctypes.c_int),
         ("full_kx", ctypes.c_int),
         ("squarings", ctypes.c_int),
+        ("btilde", ctypes.c_double * 3),
     ]
 
 
-STAB_MODELS = {"paper": 0, "fdlbm1": 1, "fdlbm2": 2}
+STAB_MODELS = {"paper": 0, "fdlbm1": 1, "fdlbm2": 2, "family": 3}
 
 _lib = None
 
@@ -145,9 +147,10 @@ def _check(rc: int):
 def make_config(*, nu: float, cfl: float = 0.0, dt: float = 0.0, eta: float = 0.01,
                 A: float = 0.5, force=(0.0, 0.0), u_wall=None, periodic_x: bool = True,
                 periodic_y: bool = True, period_x: float = 0.0, period_y: float = 0.0,
-                storage="f64", scheme: int = 1) -> Config:
+                storage="f64", scheme: int = 1, btilde=(0.0, 1.0, 0.0)) -> Config:
     """scheme 1: T2S2-FDLBM1 family (A = 1/2 FDLBM1, A = 0 T1S2); scheme 2:
-    T2S2-FDLBM2."""
+    T2S2-FDLBM2; scheme 3: the eq 2.13 family with gradient weights btilde
+    on L(f^n), L(f*), L(f^{n+1})."""
     cfg = Config()
     cfg.nu = float(nu)
     cfg.cfl = float(cfl)
@@ -165,6 +168,8 @@ def make_config(*, nu: float, cfl: float = 0.0, dt: float = 0.0, eta: float = 0.
     cfg.period_y = float(period_y)
     cfg.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     cfg.scheme = int(scheme)
+    for k in range(3):
+        cfg.btilde[k] = float(btilde[k])
     return cfg
 
 
@@ -374,7 +379,8 @@ def context_for_case(case, storage="f64", device=None, stream=None, **overrides)
 
 
 def stability_map(model, omega, r, *, eta, u=(0.0, 0.0), A=0.5, b2bar=0.5, b2tilde=0.0,
-                  nk=33, full_kx=True, squarings=30, device=None, stream=None):
+                  nk=33, full_kx=True, squarings=30, btilde=(0.0, 1.0, 0.0), device=None,
+                  stream=None):
     """Largest spectral radius of the growth matrix over the mode grid for
     each (omega[i], r[i]) (t2s2_stability_map); returns a device tensor."""
     import torch
@@ -391,6 +397,8 @@ def stability_map(model, omega, r, *, eta, u=(0.0, 0.0), A=0.5, b2bar=0.5, b2til
     prm.eta, prm.A, prm.b2bar, prm.b2tilde = float(eta), float(A), float(b2bar), float(b2tilde)
     prm.u[0], prm.u[1] = float(u[0]), float(u[1])
     prm.nk, prm.full_kx, prm.squarings = int(nk), int(bool(full_kx)), int(squarings)
+    for k in range(3):
+        prm.btilde[k] = float(btilde[k])
     with torch.cuda.device(dev):
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         _check(lib.t2s2_stability_map(ctypes.byref(prm), w.data_ptr(), rr.data_ptr(), w.numel(),

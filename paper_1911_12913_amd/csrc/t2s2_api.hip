@@ -185,8 +185,17 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   if (!(cfg->A >= 0.0 && cfg->A <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "A not in [0,1]");
   if (cfg->storage < T2S2_F64 || cfg->storage > T2S2_F16_DEV)
     return fail(T2S2_ERR_INVALID_ARG, "unknown storage");
-  if (cfg->scheme != 0 && cfg->scheme != T2S2_FDLBM1 && cfg->scheme != T2S2_FDLBM2)
+  if (cfg->scheme != 0 && cfg->scheme != T2S2_FDLBM1 && cfg->scheme != T2S2_FDLBM2 &&
+      cfg->scheme != T2S2_FAMILY)
     return fail(T2S2_ERR_INVALID_ARG, "unknown scheme");
+  if (cfg->scheme == T2S2_FAMILY) {
+    const double* b = cfg->btilde;
+    for (int k = 0; k < 3; ++k)
+      if (!(b[k] >= 0.0 && b[k] <= (k == 2 ? 0.5 : 1.0)))
+        return fail(T2S2_ERR_INVALID_ARG, "btilde: B~0, B~1 in [0,1], B~2 in [0,1/2]");
+    if (!(std::fabs(b[0] + b[1] + b[2] - 1.0) <= 1e-12))
+      return fail(T2S2_ERR_INVALID_ARG, "btilde must sum to 1 (eq 2.14a)");
+  }
   // The step kernel addresses a population plane with 32-bit byte offsets.
   if (static_cast<long long>(ny) * ((nx + 63) / 64 * 64) *
           static_cast<long long>(storage_bytes(cfg->storage)) >= (1LL << 32))
@@ -214,7 +223,7 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   c->tau = 3.0 * cfg->nu;
   c->omega = std::isinf(cfg->nu) ? 0.0 : c->dt / c->tau;
 
-  const int scheme = cfg->scheme == T2S2_FDLBM2 ? 2 : 1;
+  const int scheme = cfg->scheme == T2S2_FDLBM2 ? 2 : (cfg->scheme == T2S2_FAMILY ? 3 : 1);
   c->cfg.scheme = scheme;
   // T2S2-FDLBM2 predicts with a full step (h = dt, A = 1 in the maps below)
   // and needs the physical f^n, which is P at A = 0.
@@ -242,25 +251,38 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   p.cRs = 2.0 / (2.0 + A * w);
   p.cRe = A * w / (2.0 + A * w);
   p.cRF = A * dt / (2.0 + A * w);
+  // The family (scheme 3) also takes f at h = dt from f~ or from fbar(t_{n+1}):
+  //   U = [2 X + w f^eq + dt F] / (2 + w)  (f^n from f~^n, f^{n+1} from S2),
+  // and weighs the three gradients by btilde.
+  p.cUg = 2.0 / (2.0 + w);
+  p.cUe = w / (2.0 + w);
+  p.cUF = dt / (2.0 + w);
+  for (int k = 0; k < 3; ++k) p.b[k] = scheme == 3 ? cfg->btilde[k] : (k == 1 ? 1.0 : 0.0);
   {
     const double wc[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
     p.c64.cPg = p.cPg;
     p.c64.cQg = p.cQg;
     p.c64.cRs = p.cRs;
     p.c64.A = A;
+    p.c64.cU = p.cUg;
     for (int k = 0; k < 3; ++k) {
       p.c64.kP[k] = p.cPe * wc[k];
       p.c64.kQ[k] = p.cQe * wc[k];
       p.c64.kR[k] = p.cRe * wc[k];
+      p.c64.kU[k] = p.cUe * wc[k];
+      p.c64.b[k] = p.b[k];
     }
     p.c32.cPg = static_cast<float>(p.c64.cPg);
     p.c32.cQg = static_cast<float>(p.c64.cQg);
     p.c32.cRs = static_cast<float>(p.c64.cRs);
     p.c32.A = static_cast<float>(A);
+    p.c32.cU = static_cast<float>(p.c64.cU);
     for (int k = 0; k < 3; ++k) {
       p.c32.kP[k] = static_cast<float>(p.c64.kP[k]);
       p.c32.kQ[k] = static_cast<float>(p.c64.kQ[k]);
       p.c32.kR[k] = static_cast<float>(p.c64.kR[k]);
+      p.c32.kU[k] = static_cast<float>(p.c64.kU[k]);
+      p.c32.b[k] = static_cast<float>(p.c64.b[k]);
     }
   }
   p.half_dt = 0.5 * dt;
@@ -689,13 +711,17 @@ int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, co
                        int npoints, double* radius, void* stream) {
   g_last_error.clear();
   if (!prm) return fail(T2S2_ERR_INVALID_ARG, "NULL parameters");
-  if (prm->model < T2S2_STAB_PAPER || prm->model > T2S2_STAB_FDLBM2)
+  if (prm->model < T2S2_STAB_PAPER || prm->model > T2S2_STAB_FAMILY)
     return fail(T2S2_ERR_INVALID_ARG, "unknown stability model");
   if (!(prm->eta >= 0.0 && prm->eta <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "eta not in [0,1]");
   if (!(prm->A >= 0.0 && prm->A <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "A not in [0,1]");
   if (!std::isfinite(prm->b2bar) || !std::isfinite(prm->b2tilde) || !std::isfinite(prm->u[0]) ||
       !std::isfinite(prm->u[1]))
     return fail(T2S2_ERR_INVALID_ARG, "non-finite parameter");
+  if (prm->model == T2S2_STAB_FAMILY && !(std::isfinite(prm->btilde[0]) &&
+                                          std::isfinite(prm->btilde[1]) &&
+                                          std::isfinite(prm->btilde[2])))
+    return fail(T2S2_ERR_INVALID_ARG, "non-finite btilde");
   if (prm->nk < 2 || prm->nk > 257) return fail(T2S2_ERR_INVALID_ARG, "nk not in [2, 257]");
   if (prm->squarings < 1 || prm->squarings > 60)
     return fail(T2S2_ERR_INVALID_ARG, "squarings not in [1, 60]");
@@ -717,6 +743,7 @@ int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, co
   a.nkx = prm->full_kx ? 2 * prm->nk - 1 : prm->nk;
   a.thx0 = prm->full_kx ? -pi : 0.0;
   a.squarings = prm->squarings;
+  for (int k = 0; k < 3; ++k) a.bt[k] = prm->model == T2S2_STAB_FAMILY ? prm->btilde[k] : 0.0;
   hipError_t e = launch_stability(a, omega, r, npoints, radius, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "stability map");
   return T2S2_OK;

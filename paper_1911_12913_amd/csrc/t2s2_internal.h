@@ -53,7 +53,8 @@ struct StepParams {
   int nunits;   // groups of strips_per_block(storage, scheme) neighbouring strips
   int nblocks;  // equal ranges of the nunits * ny unit-rows, one per block
   int band;     // rows per band of the band-major strip-row order
-  int scheme;   // 1: T2S2-FDLBM1 family (eq 2.23); 2: T2S2-FDLBM2 (eq 5.23)
+  int scheme;   // 1: T2S2-FDLBM1 family (eq 2.23); 2: T2S2-FDLBM2 (eq 5.23);
+                // 3: the eq 2.13 family with gradient weights b
   void* save_s; // adjoint recompute only: S in the arithmetic type, else NULL
   const double* wx;   // [nx][2][4] dt-scaled x weights (FP64)
   const double* wy;   // [ny][2][4]
@@ -63,18 +64,22 @@ struct StepParams {
   double cPg, cPe, cPF;  // P = cPg g + cPe (feq - w) + cPF F
   double cQg, cQe, cQF;  // Q = cQg g + cQe (feq - w) + cQF F
   double cRs, cRe, cRF;  // R = cRs S + cRe (feq* - w) + cRF F*
+  double cUg, cUe, cUF;  // f at h = dt: cUg X + cUe (feq(X) - w) + cUF F(X)
+  double b[3];           // gradient weights of L(f^n), L(f*), L(f^{n+1})
   double half_dt, half_h;
   double Fx, Fy;
   double uw[4][2];
   int has_force;
   // The coefficients in the arithmetic type of the kernel: cPg, cQg, cRs,
-  // A, and per lattice-weight class c (rest, axis, diagonal) the products
-  // kP[c] = cPe w_c, kQ[c] = cQe w_c, kR[c] = cRe w_c, which multiply
-  // E = drho + rho X of f^eq - w = w E.
+  // A, cU = cUg, and per lattice-weight class c (rest, axis, diagonal) the
+  // products kP[c] = cPe w_c, kQ[c] = cQe w_c, kR[c] = cRe w_c,
+  // kU[c] = cUe w_c, which multiply E = drho + rho X of f^eq - w = w E;
+  // the family's weights b.
   template <typename Real>
   struct Coef {
-    Real cPg, cQg, cRs, A;
-    Real kP[3], kQ[3], kR[3];
+    Real cPg, cQg, cRs, A, cU;
+    Real kP[3], kQ[3], kR[3], kU[3];
+    Real b[3];
   };
   Coef<double> c64;
   Coef<float> c32;
@@ -91,8 +96,10 @@ struct AuxParams {
 
 // Von Neumann stability maps (t2s2_stability.hip).
 struct StabArgs {
-  int model;  // 0: eq 4.7; 1: eq 2.23 step, exact; 2: eq 5.23 step, exact
+  int model;  // 0: eq 4.7; 1: eq 2.23 step, exact; 2: eq 5.23 step, exact;
+              // 3: the eq 2.13 family step with gradient weights bt, exact
   double eta, A, b2bar, b2tilde, ux, uy;
+  double bt[3];
   int nkx, nky;             // k grid: theta_x = thx0 + i dthx, theta_y = j dthy
   double thx0, dthx, dthy;
   int squarings;

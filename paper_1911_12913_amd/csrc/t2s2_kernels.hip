@@ -117,17 +117,22 @@ __device__ inline Real force_term(int q, const StepParams& p, Real ux, Real uy, 
 // and force variants, and BF16 with its conversions, settle for three).
 // T2S2-FDLBM2's wider first ring (106 KB in FP64, 53 KB in FP32) admits one
 // and three blocks per CU.
+// The family's ring (140 KB in FP64, 70 KB in FP32) admits one and two.
 template <typename Store, bool kForce, bool kWalls, int kScheme>
 constexpr int kMinWaves =
     sizeof(typename Cvt<Store>::R) == 8
-        ? (kScheme == 2 ? 1 : 2)
-        : ((kScheme == 2 || kForce || kWalls || std::is_same<Store, Bf16>::value) ? 3 : 4);
+        ? (kScheme == 1 ? 2 : 1)
+        : (kScheme == 3 ? 2
+                        : ((kScheme == 2 || kForce || kWalls || std::is_same<Store, Bf16>::value)
+                               ? 3
+                               : 4));
 
 // Planes of the first LDS ring: P for T2S2-FDLBM1 (and T1S2); for
 // T2S2-FDLBM2, Q = f~^+ (the field the prediction advects) and, for the
-// eight moving directions, the physical f^n.
+// eight moving directions, the physical f^n; for the family, P, Q and the
+// eight moving directions of f^n.
 template <int kScheme>
-constexpr int kPPlanes = kScheme == 2 ? 2 * kQ - 1 : kQ;
+constexpr int kPPlanes = kScheme == 1 ? kQ : (kScheme == 2 ? 2 * kQ - 1 : 3 * kQ - 1);
 
 // The fused step, templated on the storage type, the presence of a body
 // force, of walls, on the scheme, and on kSaveS (the discrete adjoint's
@@ -136,7 +141,10 @@ constexpr int kPPlanes = kScheme == 2 ? 2 * kQ - 1 : kQ;
 //   kScheme 1: T2S2-FDLBM1 family (eq 2.23; A = 0 is T1S2);
 //   kScheme 2: T2S2-FDLBM2 (eq 5.23): f~^{n+1} = Q + dt/2 (L(f^n) + L(f^{n+1}))
 //     with f^{n+1} predicted by S = Q + dt L(Q) and unshifted with h = dt;
-//     L is linear, so the two gradients are taken as one, of T = f^n + R.
+//     L is linear, so the two gradients are taken as one, of T = f^n + R;
+//   kScheme 3: the eq 2.13 family, f~^{n+1} = Q + dt L(T) with
+//     T = b0 f^n + b1 f* + b2 f^{n+1}, f* predicted as in scheme 1 and
+//     f^{n+1} as in scheme 2.
 template <typename Store, bool kForce, bool kWalls, int kScheme, bool kSaveS = false>
 __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWaves<Store, kForce, kWalls, kScheme>)) void step_kernel(
     StepParams p) {
@@ -281,21 +289,31 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
           const Real E = d + rho * X[q];
           Real Pq = k.cPg * g[q] + k.kP[wclass(q)] * E;
           Real Qq = k.cQg * g[q] + k.kQ[wclass(q)] * E;
+          Real Fq = Real(0);
           if (kForce) {
-            const Real Fq = force_term(q, p, ux, uy, E);
+            Fq = force_term(q, p, ux, uy, E);
             Pq += static_cast<Real>(p.cPF) * Fq;
             Qq += static_cast<Real>(p.cQF) * Fq;
           }
           slotP[q * kLanes + lane] = kScheme == 2 ? Qq : Pq;
           if (kScheme == 2 && q > 0) slotP[(kQ + q - 1) * kLanes + lane] = Pq;
+          if (kScheme == 3) {
+            slotP[(kQ + q) * kLanes + lane] = Qq;
+            if (q > 0) {
+              Real Uq = k.cU * g[q] + k.kU[wclass(q)] * E;  // f^n
+              if (kForce) Uq += static_cast<Real>(p.cUF) * Fq;
+              slotP[(2 * kQ + q - 1) * kLanes + lane] = Uq;
+            }
+          }
           qnew[q] = Qq;
         }
       }
       __syncthreads();
 
-      // ---- phase 2: S and R of row p0 - 2 + t (interior nodes), R to LDS.
-      // The whole wave computes (the x taps take neighbouring lanes' centre
-      // values); only interior lanes 2..61 store.
+      // ---- phase 2: S and R of row p0 - 2 + t (interior nodes), R (or the
+      // scheme's combination T) to LDS.  The whole wave computes (the x taps
+      // take neighbouring lanes' centre values); only interior lanes 2..61
+      // store.
       {
         const int r = p0 - 2 + t;
         const bool row_ok =
@@ -310,20 +328,47 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
           for (int o = 0; o < 5; ++o)
             rb[o] = ringP + ((r + o - 2) & (kRing - 1)) * kNP * kLanes + lane;
           const auto& k = coef<Real>(p);
-          Real S[kQ];
+          // A prediction along the characteristics from ring planes
+          // [base, base + 9): S = centre + fac L(centre); then f at the
+          // predicted time, R = cs S + ke E (+ cf F), from S's moments with
+          // force shift hf.
+          auto predict = [&](int base, Real fac, Real cs, const Real* ke, double cf, double hf,
+                             Real (&S)[kQ], Real (&R)[kQ], Real& rho, Real& ux, Real& uy) {
 #pragma unroll
-          for (int q = 0; q < kQ; ++q) {
-            const Real centre = rb[2][q * kLanes];
-            Real acc = Real(0);
-            if (ex_of(q) > 0) acc = x_taps<0>(wxr, centre, acc);
-            if (ex_of(q) < 0) acc = x_taps<1>(wxr, centre, acc);
-            if (ey_of(q) != 0) {
-              const int sy = ey_of(q) > 0 ? 0 : 1;
+            for (int q = 0; q < kQ; ++q) {
+              const int pq = (base + q) * kLanes;
+              const Real centre = rb[2][pq];
+              Real acc = Real(0);
+              if (ex_of(q) > 0) acc = x_taps<0>(wxr, centre, acc);
+              if (ex_of(q) < 0) acc = x_taps<1>(wxr, centre, acc);
+              if (ey_of(q) != 0) {
+                const int sy = ey_of(q) > 0 ? 0 : 1;
 #pragma unroll
-              for (int k2 = 0; k2 < kTaps; ++k2) acc += wyr[sy * kTaps + k2] * rb[k2 + sy][q * kLanes];
+                for (int k2 = 0; k2 < kTaps; ++k2) acc += wyr[sy * kTaps + k2] * rb[k2 + sy][pq];
+              }
+              S[q] = q == 0 ? centre : centre + fac * acc;
             }
-            S[q] = q == 0 ? centre : centre + k.A * acc;
-          }
+            double s, jx, jy;
+            moment_sums(S, s, jx, jy);
+            velocity(s, jx, jy, rho, ux, uy);
+            if (kForce) {
+              ux += static_cast<Real>(hf * p.Fx);
+              uy += static_cast<Real>(hf * p.Fy);
+            }
+            const Real d = static_cast<Real>(s);
+            Real X[kQ];
+            eq_brackets(ux, uy, X);
+            R[0] = Real(0);
+#pragma unroll
+            for (int q = 1; q < kQ; ++q) {
+              const Real E = d + rho * X[q];
+              Real Rq = cs * S[q] + ke[wclass(q)] * E;
+              if (kForce) Rq += static_cast<Real>(cf) * force_term(q, p, ux, uy, E);
+              R[q] = Rq;
+            }
+          };
+          Real S[kQ], R[kQ], rho, ux, uy;
+          predict(0, k.A, k.cRs, k.kR, p.cRF, p.half_h, S, R, rho, ux, uy);
           if (kSaveS && lane_o && col_interior && r >= y0 && r < y1) {
             Real* sv = static_cast<Real*>(p.save_s);
             const unsigned boff =
@@ -332,40 +377,32 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
 #pragma unroll
             for (int q = 0; q < kQ; ++q) *at_byte(sv + q * plane, boff) = S[q];
           }
-          double s, jx, jy;
-          moment_sums(S, s, jx, jy);
-          Real rho, ux, uy;
-          velocity(s, jx, jy, rho, ux, uy);
-          if (kForce) {
-            ux += static_cast<Real>(p.half_h * p.Fx);
-            uy += static_cast<Real>(p.half_h * p.Fy);
-          }
-          const Real d = static_cast<Real>(s);
-          Real X[kQ];
-          eq_brackets(ux, uy, X);
-          Real R[kQ];
-          R[0] = Real(0);
+          // The family's second prediction: f^{n+1} from Q with h = dt.
+          Real R2[kQ], rho2 = Real(1), ux2 = Real(0), uy2 = Real(0);
 #pragma unroll
-          for (int q = 1; q < kQ; ++q) {
-            const Real E = d + rho * X[q];
-            Real Rq = k.cRs * S[q] + k.kR[wclass(q)] * E;
-            if (kForce) Rq += static_cast<Real>(p.cRF) * force_term(q, p, ux, uy, E);
-            R[q] = Rq;
+          for (int q = 0; q < kQ; ++q) R2[q] = Real(0);
+          if constexpr (kScheme == 3) {
+            Real S2[kQ];
+            predict(kQ, Real(1), k.cU, k.kU, p.cUF, p.half_dt, S2, R2, rho2, ux2, uy2);
           }
-          // T2S2-FDLBM2 stores T = f^n + R: the full step takes the
-          // gradient of both at once.
-          auto with_fn = [&](int q, int row, int ln, Real v) {
-            if (kScheme == 2)
-              v += ringP[(row & (kRing - 1)) * kNP * kLanes + (kQ + q - 1) * kLanes + ln];
-            return v;
+          // T, the field whose gradient the full step takes: R (scheme 1),
+          // f^n + R (scheme 2, halved in phase 3), b0 f^n + b1 R + b2 R2
+          // (scheme 3); f^n of (row, ln) from the ring.
+          auto t_of = [&](int q, int row, int ln, Real r1, Real r2) {
+            const Real* slot = ringP + (row & (kRing - 1)) * kNP * kLanes + ln;
+            if (kScheme == 2) return r1 + slot[(kQ + q - 1) * kLanes];
+            if (kScheme == 3)
+              return k.b[0] * slot[(2 * kQ + q - 1) * kLanes] + k.b[1] * r1 + k.b[2] * r2;
+            return r1;
           };
           if (lane_r && col_interior) {
             Real* slotR = ringR + (r & (kRing - 1)) * (kQ - 1) * kLanes;
 #pragma unroll
-            for (int q = 1; q < kQ; ++q) slotR[(q - 1) * kLanes + lane] = with_fn(q, r, lane, R[q]);
+            for (int q = 1; q < kQ; ++q) slotR[(q - 1) * kLanes + lane] = t_of(q, r, lane, R[q], R2[q]);
             // Wall nodes whose nearest interior node is this one (eq 3.10
-            // on f(t*); corners take the diagonal neighbour).  Physical f
-            // carries no force shift: u_f = sum xi R / rho = u*.
+            // on f(t*) and f(t_{n+1}); corners take the diagonal
+            // neighbour).  Physical f carries no force shift:
+            // u_f = sum xi R / rho = u*.
             const bool src_yb = !p.per_y && r == 1;
             const bool src_yt = !p.per_y && r == ny - 2;
             if (kWalls && (src_xl || src_xr || src_yb || src_yt)) {
@@ -376,13 +413,19 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
                   if (dx == 0 && dy == 0) continue;
                   double ub, vb;
                   wall_velocity(p, c + dx, r + dy, ub, vb);
-                  Real sh[kQ];
+                  Real sh[kQ], sh2[kQ];
                   nee_shift(static_cast<double>(rho), static_cast<double>(ux),
                             static_cast<double>(uy), ub, vb, sh);
+#pragma unroll
+                  for (int q = 0; q < kQ; ++q) sh2[q] = Real(0);
+                  if constexpr (kScheme == 3)
+                    nee_shift(static_cast<double>(rho2), static_cast<double>(ux2),
+                              static_cast<double>(uy2), ub, vb, sh2);
                   Real* slotW = dy == 1 ? topR : ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
 #pragma unroll
                   for (int q = 1; q < kQ; ++q)
-                    slotW[(q - 1) * kLanes + lane + dx] = with_fn(q, r + dy, lane + dx, R[q] + sh[q]);
+                    slotW[(q - 1) * kLanes + lane + dx] =
+                        t_of(q, r + dy, lane + dx, R[q] + sh[q], R2[q] + sh2[q]);
                 }
               }
             }
@@ -700,6 +743,8 @@ hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
   const bool walls = !p.per_x || !p.per_y;
   if (p.scheme == 2)
     launch_fused<Store, 2>(p, g, b, s, walls);
+  else if (p.scheme == 3)
+    launch_fused<Store, 3>(p, g, b, s, walls);
   else
     launch_fused<Store, 1>(p, g, b, s, walls);
   hipError_t e = hipGetLastError();
@@ -756,7 +801,9 @@ int occupancy_s(bool force, bool walls) {
 
 template <typename Store>
 int occupancy_t(bool force, bool walls, int scheme) {
-  return scheme == 2 ? occupancy_s<Store, 2>(force, walls) : occupancy_s<Store, 1>(force, walls);
+  if (scheme == 2) return occupancy_s<Store, 2>(force, walls);
+  if (scheme == 3) return occupancy_s<Store, 3>(force, walls);
+  return occupancy_s<Store, 1>(force, walls);
 }
 
 int step_blocks_per_cu(int storage, bool force, bool walls, int scheme) {

@@ -11,6 +11,8 @@
 //     dt):  G = J_Q - rS J_R (I - A rS) J_P;
 //   model 2: the exact linearisation of the eq 5.23 step:
 //     G = J_Q - (rS/2) (J_f + J_R1 (I - rS) J_Q);
+//   model 3: the exact linearisation of the eq 2.13 family step:
+//     G = J_Q - rS (b0 J_f + b1 J_R (I - A rS) J_P + b2 J_R1 (I - rS) J_Q);
 // with Gamma = d f^eq / d f, J_X = c_Xg I + c_Xe Gamma, and S the symbol of
 // dx xi_q . D of the mixed difference (eq 4.8, imaginary unit restored in
 // the exponentials).  The advection symbol multiplies from the left (it
@@ -86,7 +88,7 @@ __device__ inline void for_elems(int lane, F f) {
 __global__ __launch_bounds__(64) void stability_kernel(StabArgs a, const double* omega_p,
                                                         const double* r_p, double* radius) {
   __shared__ double gam[kN2];
-  __shared__ cplx X[kN2], T[kN2];
+  __shared__ cplx X[kN2], T[kN2], T2[kN2];
   __shared__ cplx sym[kN];
   const int lane = threadIdx.x;
   const int point = blockIdx.x;
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(64) void stability_kernel(StabArgs a, const double*
   const double cQg = (2 - w) / (2 + w), cQe = 2 * w / (2 + w);
   const double cRs = a.model == 2 ? 2 / (2 + w) : 2 / (2 + A * w);
   const double cRe = a.model == 2 ? w / (2 + w) : A * w / (2 + A * w);
-  const double cFg = 2 / (2 + w), cFe = w / (2 + w);  // f from f~ (A = 0)
+  const double cFg = 2 / (2 + w), cFe = w / (2 + w);  // f from f~ (A = 0); R at h = dt
   __syncthreads();
 
   double best = 0.0;
@@ -168,6 +170,28 @@ __global__ __launch_bounds__(64) void stability_kernel(StabArgs a, const double*
       }
       // G in T; copy to X
       for_elems(lane, [&](int i, int j) { X[i * kN + j] = T[i * kN + j]; });
+      __syncthreads();
+    } else if (a.model == 3) {
+      // T = (I - A rS) J_P, T2 = (I - rS) J_Q; then
+      // X = J_Q - rS (b0 J_f + b1 J_R T + b2 J_R1 T2), J_R1 = cFg I + cFe Gamma.
+      for_elems(lane, [&](int i, int j) {
+        const double d = i == j ? 1.0 : 0.0, g = gam[i * kN + j];
+        T[i * kN + j] = cscale(csub({1.0, 0.0}, cscale(sym[i], A * r)), cPg * d + cPe * g);
+        T2[i * kN + j] = cscale(csub({1.0, 0.0}, cscale(sym[i], r)), cQg * d + cQe * g);
+      });
+      __syncthreads();
+      for_elems(lane, [&](int i, int j) {
+        cplx m1{0.0, 0.0}, m2{0.0, 0.0};
+        for (int k = 0; k < kN; ++k) {
+          const double dk = i == k ? 1.0 : 0.0, gk = gam[i * kN + k];
+          m1 = cadd(m1, cscale(T[k * kN + j], cRs * dk + cRe * gk));
+          m2 = cadd(m2, cscale(T2[k * kN + j], cFg * dk + cFe * gk));
+        }
+        const double d = i == j ? 1.0 : 0.0, g = gam[i * kN + j];
+        cplx m = cadd(cscale(m1, a.bt[1]), cscale(m2, a.bt[2]));
+        m = cadd(m, {a.bt[0] * (cFg * d + cFe * g), 0.0});
+        X[i * kN + j] = csub({cQg * d + cQe * g, 0.0}, cmul(cscale(sym[i], r), m));
+      });
       __syncthreads();
     } else {
       // T = (I - c rS) J, with (c, J) = (A, J_P) for model 1 and (1, J_Q) for model 2.

@@ -30,18 +30,31 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_config_struct_layout():
-    # 5 doubles, force[2], u_wall[4][2], 2 ints, 2 doubles, 2 ints
-    assert ctypes.sizeof(t2s2.Config) == 8 * 5 + 16 + 64 + 8 + 16 + 8
+    # 5 doubles, force[2], u_wall[4][2], 2 ints, 2 doubles, 2 ints, btilde[3]
+    assert ctypes.sizeof(t2s2.Config) == 8 * 5 + 16 + 64 + 8 + 16 + 8 + 24
     assert t2s2.Config.scheme.offset == 8 * 5 + 16 + 64 + 8 + 16 + 4
+    assert t2s2.Config.btilde.offset == 8 * 5 + 16 + 64 + 8 + 16 + 8
 
 
 def test_scheme_validation():
     lib = t2s2.load_library()
-    for scheme, ok in ((0, True), (1, True), (2, True), (3, False), (-1, False)):
+    for scheme, ok in ((0, True), (1, True), (2, True), (3, True), (4, False), (-1, False)):
         rc, h = _create(_good_cfg(scheme=scheme), _axis(20), _axis(20))
         assert (rc == t2s2.OK) == ok, scheme
         if h.value:
             lib.t2s2_destroy(h)
+    # the family's gradient weights (eq 2.14a and the paper's ranges)
+    for bt, ok in (((0.25, 0.5, 0.25), True), ((1.0, 0.0, 0.0), True), ((0.5, 0.0, 0.5), True),
+                   ((0.3, 0.3, 0.3), False), ((0.2, 0.2, 0.6), False), ((-0.1, 1.1, 0.0), False),
+                   ((0.5, float("nan"), 0.5), False)):
+        rc, h = _create(_good_cfg(scheme=3, btilde=bt), _axis(20), _axis(20))
+        assert (rc == t2s2.OK) == ok, bt
+        if h.value:
+            lib.t2s2_destroy(h)
+    # the other schemes ignore btilde
+    rc, h = _create(_good_cfg(scheme=1, btilde=(9.0, 9.0, 9.0)), _axis(20), _axis(20))
+    assert rc == t2s2.OK
+    lib.t2s2_destroy(h)
 
 
 def _create(cfg, x, y):
@@ -148,8 +161,15 @@ def test_stability_map_argument_checks_without_device():
         return ctypes.byref(p)
 
     assert lib.t2s2_stability_map(prm(), None, None, 0, None, None) == t2s2.OK
-    for bad in (dict(model=3), dict(eta=1.5), dict(A=-0.1), dict(nk=1), dict(nk=2000),
+    for bad in (dict(model=4), dict(eta=1.5), dict(A=-0.1), dict(nk=1), dict(nk=2000),
                 dict(squarings=0), dict(squarings=61), dict(b2bar=math.nan)):
         assert lib.t2s2_stability_map(prm(**bad), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
     assert lib.t2s2_stability_map(prm(), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
     assert lib.t2s2_stability_map(None, None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
+    fam = t2s2.StabilityParams()
+    fam.model, fam.eta, fam.A, fam.nk, fam.full_kx, fam.squarings = 3, 0.1, 0.5, 9, 1, 30
+    fam.btilde[0], fam.btilde[1], fam.btilde[2] = 0.25, math.inf, 0.25
+    assert lib.t2s2_stability_map(ctypes.byref(fam), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
+    fam.btilde[1] = 0.5   # valid: fails only on the NULL arrays
+    assert lib.t2s2_stability_map(ctypes.byref(fam), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
+    assert lib.t2s2_stability_map(ctypes.byref(fam), None, None, 0, None, None) == t2s2.OK

@@ -312,6 +312,69 @@ def test_fdlbm2_fp32_error_vs_oracle():
     assert err <= 3e-5
 
 
+# ------------------------- the eq 2.13 family (gradient weights btilde)
+
+FAMILY = [(0.5, (0.25, 0.5, 0.25)), (0.3, (0.15, 0.5, 0.35))]
+
+
+@pytest.mark.parametrize("A,bt", FAMILY)
+def test_family_periodic_matches_oracle(A, bt):
+    """The family step (scheme 3) on the periodic 150x70 Taylor-Green with
+    seeded noise, CFL 0.5, 120 steps, two second-order members."""
+    case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.5, eta=0.05)
+    phi0 = oracle.init(case) + W.random_state((9, 70, 150), 1e-5, 8)
+    ref = oracle.run(case, phi0, 120, scheme=3, btilde=bt, A=A)
+    _, g, d, u, v = _gpu_run(case, phi0, 120, scheme=3, btilde=bt, A=A)
+    _compare(case, g, d, u, v, ref)
+
+
+@pytest.mark.parametrize("blocks", ["8", "40"])
+def test_family_walled_cavity_matches_oracle(blocks, monkeypatch):
+    """The family step on the ragged 130x65 cavity (both predictions carry
+    the wall extrapolation), CFL 0.5, 150 steps, 8 and 40 block ranges."""
+    monkeypatch.setenv("T2S2_BLOCKS", blocks)
+    case = _ragged_cavity(0.5)
+    phi0 = oracle.init(case)
+    A, bt = FAMILY[0]
+    ref = oracle.run(case, phi0, 150, scheme=3, btilde=bt, A=A)
+    _, g, d, u, v = _gpu_run(case, phi0, 150, scheme=3, btilde=bt, A=A)
+    _compare(case, g, d, u, v, ref)
+
+
+def test_family_forced_channel_matches_oracle():
+    """The family step on the force-driven channel, 400 steps."""
+    case = W.poiseuille_case(dt_over_y1=0.5, eta=0.1)
+    phi0 = oracle.init(case)
+    A, bt = FAMILY[1]
+    ref = oracle.run(case, phi0, 400, scheme=3, btilde=bt, A=A)
+    _, g, d, u, v = _gpu_run(case, phi0, 400, scheme=3, btilde=bt, A=A)
+    _compare(case, g, d, u, v, ref)
+
+
+def test_family_010_is_bitwise_fdlbm1_on_the_gpu():
+    """btilde = (0, 1, 0) makes T = 0 f^n + R + 0 R2 = R exactly: the family
+    kernel reproduces the T2S2-FDLBM1 kernel's state bit for bit."""
+    case = _ragged_cavity(0.5)
+    phi0 = oracle.init(case)
+    _, g1, *_ = _gpu_run(case, phi0, 60, scheme=1)
+    _, g3, *_ = _gpu_run(case, phi0, 60, scheme=3, btilde=(0.0, 1.0, 0.0))
+    assert np.array_equal(g1, g3)
+
+
+def test_family_fp32_error_vs_oracle():
+    """The family step with FP32 deviation storage: velocity error against
+    the FP64 oracle, reported and bounded."""
+    case = W.tgv_case(64, 64, u0=0.01, nu=0.01, cfl=0.5, eta=0.01)
+    phi0 = oracle.init(case)
+    A, bt = FAMILY[0]
+    ref = oracle.run(case, phi0, 400, scheme=3, btilde=bt, A=A)
+    _, g, d, u, v = _gpu_run(case, phi0, 400, storage="f32", scheme=3, btilde=bt, A=A)
+    _, ur, vr = oracle.moments(case, ref)
+    err = _rel(np.stack([u, v]), np.stack([ur, vr]))
+    print(f"    f32 family: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
+    assert err <= 3e-5
+
+
 # -------------------------------- FP32 storage: two strips per block
 
 @pytest.mark.parametrize("blocks", ["8", "24"])
