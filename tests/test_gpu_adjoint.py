@@ -2,6 +2,7 @@
 autograd, and the sqrt(N)-checkpointed rollout gradient against central
 finite differences (FP64)."""
 import math
+import time
 
 import numpy as np
 import pytest
@@ -166,23 +167,33 @@ def test_rollout_gradient_vs_central_differences_fp64(nsteps):
     assert e_dir < 1e-6 and e_nu < 1e-6
 
 
-def test_fp32_adjoint_against_fp64_adjoint():
-    """The FP32 rollout gradient of the 513x513 workload, reported against the
-    FP64 one (200 steps)."""
+@pytest.mark.parametrize("nsteps", [200, 2000])
+def test_fp32_adjoint_against_fp64_adjoint(nsteps):
+    """The FP32 rollout gradient of the 513x513 workload (at N = 2000 the
+    differentiation configuration itself: FP32, sqrt(N) checkpoints),
+    reported against the FP64 one, with the wall time of the FP32 rollout
+    (forward and backward)."""
     case = _cavity513()
     grads = {}
     for storage in ("f64", "f32"):
-        spec, rho0, loss_of = _probe_loss_fn(case, 200, storage)
+        spec, rho0, loss_of = _probe_loss_fn(case, nsteps, storage)
         u0, v0 = W.gaussian_velocity(case.nx, case.ny, std=1e-3, seed=1)
         gu = _dev(u0).requires_grad_(True)
         gv = _dev(v0).requires_grad_(True)
         gnu = torch.tensor(case.nu, dtype=torch.float64, device="cuda:0", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         U, V = T2S2Rollout.apply(rho0, gu, gv, gnu, spec)
         loss_of(U, V).backward()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
         grads[storage] = (gu.grad.cpu().numpy(), gv.grad.cpu().numpy(), gnu.grad.item())
+        print(f"    {storage} rollout of {nsteps} steps, forward + backward: {secs:.3f} s",
+              flush=True)
     e_u = W.rel_l2(np.stack(grads["f32"][:2]), np.stack(grads["f64"][:2]))
     e_nu = abs(grads["f32"][2] - grads["f64"][2]) / abs(grads["f64"][2])
-    print(f"    FP32 vs FP64 adjoint: dL/du0 rel L2 {e_u:.2e}, dL/dnu rel {e_nu:.2e}", flush=True)
+    print(f"    FP32 vs FP64 adjoint, {nsteps} steps: dL/du0 rel L2 {e_u:.2e}, "
+          f"dL/dnu rel {e_nu:.2e}", flush=True)
     assert e_u < 1e-2 and e_nu < 1e-2
 
 
