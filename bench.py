@@ -137,9 +137,11 @@ def main(argv=None):
     ap.add_argument("--forms", default="f32,bf16,f16",
                     help="reduced-storage forms run after the headline one, each with the "
                          "same steps; their speed-up and velocity error are reported")
-    ap.add_argument("--cpu-steps", type=int, default=2,
-                    help="oracle steps timed on the host (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=8,
+                    help="oracle steps timed on the host with --cpu-threads threads (0 = skip)")
     ap.add_argument("--cpu-threads", type=int, default=None)
+    ap.add_argument("--cpu-single-steps", type=int, default=1,
+                    help="oracle steps timed on one host thread (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed region, one plain device copy of this many bytes "
                          "(reference dispatch for scaling rocprofv3 memory counters)")
@@ -200,6 +202,13 @@ def main(argv=None):
                "kind": "oracle",
                "sample": f"{args.cpu_steps} FP64 oracle steps of the same {n}x{n} TGV grid "
                          f"({secs:.1f} s, {used} OpenMP threads)"}
+        if args.cpu_single_steps > 0:
+            secs1, used1 = cpu_leg(case, args.cpu_single_steps, 1)
+            cpu["single_thread"] = {
+                "value": nodes * args.cpu_single_steps / secs1 / 1e6, "unit": "MLUPS",
+                "cores": used1,
+                "sample": f"{args.cpu_single_steps} FP64 oracle step(s) of the same grid "
+                          f"({secs1:.1f} s, 1 thread)"}
 
     rec = {
         "metric": METRIC,
