@@ -52,12 +52,23 @@ def _compare(case, g_gpu, d, u, v, phi_ref, tol=TOL):
 
 
 def test_tgv32_1000_steps_matches_oracle():
-    """Taylor-Green 32x32 on [0, 2pi]^2, U0 0.01, nu 0.01, CFL 0.5, 1000 steps."""
+    """Taylor-Green 32x32 on [0, 2pi]^2, U0 0.01, nu 0.01, CFL 0.5, 1000 steps;
+    then E(u) of eq 3.6 against the closed-form decay of eq 3.4, from the
+    GPU reduction, equals the oracle's."""
     case = W.tgv_case(32, 32, u0=0.01, nu=0.01, cfl=0.5, eta=0.01)
     phi0 = oracle.init(case)
     ref = oracle.run(case, phi0, 1000)
-    _, g, d, u, v = _gpu_run(case, phi0, 1000)
+    ctx, g, d, u, v = _gpu_run(case, phi0, 1000)
     _compare(case, g, d, u, v, ref)
+    t = 1000 * oracle.time_step(case)
+    _, ue, ve, _ = W.tgv_fields(case.x, case.y, 1.0, 1.0, 0.01, case.nu, t)
+    _, uo, vo = oracle.moments(case, ref)
+    e_oracle = math.sqrt(np.sum((uo - ue) ** 2 + (vo - ve) ** 2) / np.sum(ue ** 2 + ve ** 2))
+    e_gpu = ctx.velocity_error(torch.from_numpy(ue), torch.from_numpy(ve))["gre"]
+    print(f"    tgv32 E(u) vs eq 3.4 at t = {t:.2f}: gpu {e_gpu:.6e} oracle {e_oracle:.6e}",
+          flush=True)
+    assert e_gpu == pytest.approx(e_oracle, rel=1e-9)
+    assert e_gpu < 0.03
 
 
 def test_cavity65_seeded_matches_oracle():
