@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* n
 //   the ring, lamQ = mu, and lam_n through the P and Q stages.
 // The d/d omega partials sum over the nodes each lane outputs, once each.
 template <typename Store>
-__global__ __launch_bounds__(256) void adj_strip(AdjParams a, const Store* g,
+__global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
                                                  const typename Cvt<Store>::R* mu,
                                                  typename Cvt<Store>::R* lam_out, double* partial,
                                                  int nstrips) {
@@ -250,18 +250,29 @@ __global__ __launch_bounds__(256) void adj_strip(AdjParams a, const Store* g,
   double dw = 0.0;
   for (int i = threadIdx.x; i < kRing * kQ * kLanes; i += 256) ring[i] = Real(0);
 
-  // lamR of population q at (c, y) from the rows around (y taps only): the
-  // wall rows' lamR, and the y part of the interior rows'.
-  auto lamR_y = [&](int q, int c, bool col_int, int y) {
+  // lamR of population q at (c, y) from the rows around (y taps only, over
+  // interior source rows): the wall rows' lamR, and the y part of the
+  // interior rows'.  y is a row inside the grid; the caller zeroes wall
+  // columns.  In FP32 every tap loads (from row y when its source row is
+  // not interior, with weight 0), so the four loads issue together; FP64
+  // skips those loads, which keeps its registers within two waves per SIMD.
+  auto lamR_y = [&](int q, int c, int y) {
     Real acc = Real(0);
-    if (ey_of(q) == 0 || !col_int) return acc;
+    if (ey_of(q) == 0) return acc;
     const int s = ey_of(q) > 0 ? 0 : 1;
 #pragma unroll
     for (int k = 0; k < kTaps; ++k) {
       const int yi = along(y, -tap_offset(s, k), ny, a.per_y);
-      if (yi >= 0 && (a.per_y || (yi >= 1 && yi <= ny - 2)))
-        acc += WY[yi * kWeightsPerNode + s * kTaps + k] *
-               mu[q * plane + static_cast<long long>(yi) * a.pitch + c];
+      const bool rok = yi >= 0 && (a.per_y || (yi >= 1 && yi <= ny - 2));
+      if constexpr (sizeof(Real) == 8) {
+        if (rok)
+          acc += WY[yi * kWeightsPerNode + s * kTaps + k] *
+                 mu[q * plane + static_cast<long long>(yi) * a.pitch + c];
+      } else {
+        const int yc = rok ? yi : y;
+        const Real w = rok ? WY[yc * kWeightsPerNode + s * kTaps + k] : Real(0);
+        acc += w * mu[q * plane + static_cast<long long>(yc) * a.pitch + c];
+      }
     }
     return acc;
   };
@@ -310,7 +321,8 @@ __global__ __launch_bounds__(256) void adj_strip(AdjParams a, const Store* g,
             // x part: sources (c - o_k, r), o_k the tap offset
             Real acc = Real(0);
             if (ex_of(q) != 0) {
-              const Real m = nin ? mu[q * plane + roff] : Real(0);
+              const Real mv = mu[q * plane + roff];
+              const Real m = nin ? mv : Real(0);
               if (ex_of(q) > 0) {  // o = -2, -1, 0, +1
                 acc = from_above(from_above(wx[0] * m)) + from_above(wx[1] * m) + wx[2] * m +
                       from_below(wx[3] * m);
@@ -319,7 +331,8 @@ __global__ __launch_bounds__(256) void adj_strip(AdjParams a, const Store* g,
                       from_below(from_below(wx[7] * m));
               }
             }
-            lr[q] = acc + (row_int ? lamR_y(q, c, col_int, r) : Real(0));
+            const Real ly = row_int ? lamR_y(q, c, r) : Real(0);
+            lr[q] = acc + (col_int ? ly : Real(0));
           }
           // lamR of the x-wall neighbour (its own lane computed it above)
           Real lw[kQ];
@@ -352,7 +365,7 @@ __global__ __launch_bounds__(256) void adj_strip(AdjParams a, const Store* g,
               Real lb[kQ];
               lb[0] = Real(0);
 #pragma unroll
-              for (int q = 1; q < kQ; ++q) lb[q] = lamR_y(q, c, col_int, by);
+              for (int q = 1; q < kQ; ++q) lb[q] = lamR_y(q, c, by);
               add_wall(c, by, lb);
             }
             Real feq[kQ];
