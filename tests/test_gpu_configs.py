@@ -4,6 +4,7 @@ and the precision-form errors of the large cavity.
 * Taylor-Green 4096 x 4096 (the throughput workload of bench.py, in the
   launch configuration bench.py times): two FP64 steps against the oracle on
   the whole grid; the FP32 storage form's error at the same point.
+* The same grid: step time of the three schemes.
 * Lid-driven cavity 257 x 257 (tanh mesh, Re 1000, CFL 0.9): 5000 steps
   against the oracle; HIP-graph stepping bitwise equal to plain launches,
   with eager work between replays; MLUPS with and without the graph.
@@ -74,6 +75,33 @@ def test_tgv4096_bench_configuration_matches_oracle(monkeypatch):
             assert eg <= tol_g
         _say(msg)
         assert ev <= tol_v
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_tgv4096_scheme_throughput(storage, monkeypatch):
+    """Step time of the three schemes on the 4096^2 Taylor-Green workload
+    (T2S2-FDLBM1, T2S2-FDLBM2, and the eq 2.13 family with B~ = (1/4,
+    1/2, 1/4)), 100 steps each after 10 warm-up steps; reported.  All three
+    keep the vortex bounded (max |u| within the initial amplitude)."""
+    monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+    case = W.tgv_case(4096, 4096, u0=0.01, nu=1e-4, cfl=0.9, eta=0.01)
+    for scheme, kw in ((1, {}), (2, {}), (3, dict(btilde=(0.25, 0.5, 0.25)))):
+        ctx = t2s2.context_for_case(case, storage=storage, scheme=scheme, **kw)
+        ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
+        ctx.step(10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.step(100)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 100 * 1e3
+        d = ctx.diagnostics()
+        _say(f"    tgv4096 {storage} scheme {scheme}: {us:.1f} us/step, "
+             f"{case.nx * case.ny / us:.0f} MLUPS, max|u| {d['max_speed']:.6e}")
+        assert 0.0 < d["max_speed"] <= 0.01
         ctx.close()
         del ctx
         torch.cuda.empty_cache()
