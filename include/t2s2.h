@@ -187,6 +187,16 @@ int t2s2_diagnostics(t2s2_ctx* ctx, double out[T2S2_NDIAG]);
 int t2s2_velocity_error(t2s2_ctx* ctx, const double* ux_ref, const double* uy_ref,
                         double out[3]);
 
+/* Host copies of the stencil weights computed at create: the dt-scaled
+ * taps of L = -dt xi_a d/dx_a (the mixed difference of eqs 2.36-2.38, eta
+ * the upwind weight, times the metric 1/x'(i) of the mesh), per node and
+ * sign of xi_a.  wx[8 i + 4 s + k] for x node i: s = 0 (xi_a > 0) taps at
+ * offsets -2, -1, 0, +1; s = 1 (xi_a < 0) at -1, 0, +1, +2; zero on wall
+ * nodes; central at the first interior node of a walled axis.  wy
+ * likewise.  wx, wy: host arrays of 8 nx and 8 ny doubles, either may be
+ * NULL.  No device call.  Errors: INVALID_ARG (NULL context). */
+int t2s2_stencil_weights(const t2s2_ctx* ctx, double* wx, double* wy);
+
 /* Relaxation parameter omega = dt / tau in use (0 without collision). */
 double t2s2_omega(const t2s2_ctx* ctx);
 

@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH):
         "t2s2_read_distributions": (i, [vp, vp]),
         "t2s2_diagnostics": (i, [vp, ctypes.POINTER(ctypes.c_double)]),
         "t2s2_velocity_error": (i, [vp, vp, vp, ctypes.POINTER(ctypes.c_double)]),
+        "t2s2_stencil_weights": (i, [vp, vp, vp]),
         "t2s2_omega": (d, [vp]),
         "t2s2_adjoint_state_bytes": (sz, [vp]),
         "t2s2_adjoint_scratch_bytes": (sz, [vp]),
@@ -132,7 +133,7 @@ def exported_symbols() -> Sequence[str]:
             "t2s2_init_macro", "t2s2_init_distributions", "t2s2_step", "t2s2_graph_capture",
             "t2s2_graph_step", "t2s2_current",
             "t2s2_steps_taken", "t2s2_dt", "t2s2_moments", "t2s2_read_distributions",
-            "t2s2_diagnostics", "t2s2_velocity_error", "t2s2_omega", "t2s2_adjoint_state_bytes",
+            "t2s2_diagnostics", "t2s2_velocity_error", "t2s2_stencil_weights", "t2s2_omega", "t2s2_adjoint_state_bytes",
             "t2s2_adjoint_scratch_bytes", "t2s2_bind_adjoint", "t2s2_adjoint_seed_velocity",
             "t2s2_adjoint_step", "t2s2_adjoint_init_macro", "t2s2_adjoint_read",
             "t2s2_adjoint_load", "t2s2_stability_map", "t2s2_destroy", "t2s2_last_error")

@@ -589,6 +589,14 @@ int t2s2_velocity_error(t2s2_ctx* c, const double* ux_ref, const double* uy_ref,
   return T2S2_OK;
 }
 
+int t2s2_stencil_weights(const t2s2_ctx* c, double* wx, double* wy) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (wx) std::copy(c->wx.begin(), c->wx.end(), wx);
+  if (wy) std::copy(c->wy.begin(), c->wy.end(), wy);
+  return T2S2_OK;
+}
+
 double t2s2_omega(const t2s2_ctx* c) { return c ? c->omega : 0.0; }
 
 size_t t2s2_adjoint_state_bytes(const t2s2_ctx* c) {
