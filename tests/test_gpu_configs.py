@@ -130,20 +130,23 @@ def test_cavity257_5000_steps_matches_oracle():
     assert eg <= 1e-12 and ev <= 1e-12
 
 
-@pytest.mark.parametrize("kind", ["cavity65", "tgv48x40"])
-def test_graph_stepping_is_bitwise_plain_stepping(kind):
+@pytest.mark.parametrize("kind,scheme", [("cavity65", 1), ("tgv48x40", 1), ("cavity65", 2),
+                                         ("cavity65", 3)])
+def test_graph_stepping_is_bitwise_plain_stepping(kind, scheme):
     """A captured multi-step HIP graph gives bitwise the state of plain
     launches, replay after replay, with plain steps and host synchronisation
-    between the replays (which also leave the state in the other buffer)."""
+    between the replays (which also leave the state in the other buffer);
+    for each scheme (the family with B~ = (1/4, 1/2, 1/4))."""
     if kind == "cavity65":
         case = W.cavity_case(64, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
     else:
         case = W.tgv_case(48, 40, u0=0.05, nu=0.01, cfl=0.6, eta=0.05)
     phi0 = oracle.init(case)
-    _say(f"[gpu] graph stepping {kind}")
+    _say(f"[gpu] graph stepping {kind} scheme {scheme}")
+    kw = dict(scheme=scheme, btilde=(0.25, 0.5, 0.25)) if scheme == 3 else dict(scheme=scheme)
     s_plain, s_graph = torch.cuda.Stream(), torch.cuda.Stream()
-    a = t2s2.context_for_case(case, stream=s_plain)
-    b = t2s2.context_for_case(case, stream=s_graph)
+    a = t2s2.context_for_case(case, stream=s_plain, **kw)
+    b = t2s2.context_for_case(case, stream=s_graph, **kw)
     for c in (a, b):
         c.init_distributions(torch.from_numpy(phi0))
     b.graph_capture(10)

@@ -453,15 +453,17 @@ def test_zero_steps_is_identity():
 
 
 @pytest.mark.parametrize("eta", [0.0, 1.0])
-@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("scheme", [1, 2, 3])
 def test_eta_extremes_walled(eta, scheme):
     """Pure central (eta = 0) and pure second-order upwind (eta = 1)
-    differences on the walled ragged cavity, both schemes, 100 steps."""
+    differences on the walled ragged cavity, the three schemes (the family
+    with B~ = (1/4, 1/2, 1/4)), 100 steps."""
     case = _ragged_cavity(0.5)
     case.eta = eta
     phi0 = oracle.init(case)
-    ref = oracle.run(case, phi0, 100, scheme=scheme)
-    _, g, d, u, v = _gpu_run(case, phi0, 100, scheme=scheme)
+    kw = dict(btilde=FAMILY[0][1]) if scheme == 3 else {}
+    ref = oracle.run(case, phi0, 100, scheme=scheme, **kw)
+    _, g, d, u, v = _gpu_run(case, phi0, 100, scheme=scheme, **kw)
     _compare(case, g, d, u, v, ref)
 
 
