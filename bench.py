@@ -17,7 +17,10 @@ forms (deviations stored in FP32, BF16 or FP16, FP32 arithmetic, FP64
 moment sums) then run the same steps on the same grid; each reports its
 MLUPS, its speed-up over the FP64 line and the relative L2 error of its
 final velocity field against the FP64 result (which matches the oracle to
-round-off) and against the closed-form decay of eq 3.4.
+round-off) and against the closed-form decay of eq 3.4.  Guo's T1S2-FDLBM
+(A = 0, the single-stencil kernel) runs last on the same grid in FP64 at
+CFL 0.25, inside its stable range, for the cost of one scheme against the
+other.
 """
 from __future__ import annotations
 
@@ -78,7 +81,7 @@ def W_tgv_fields(case, t):
     return W.tgv_fields(case.x, case.y, m["k1"], m["k2"], m["u0"], case.nu, t)
 
 
-def gpu_leg(case, storage, steps, warmup):
+def gpu_leg(case, storage, steps, warmup, **overrides):
     """One storage form on the GPU: warmup steps, then `steps` timed steps
     between two HIP events recorded on the library's launch stream.  Returns
     the elapsed ms, the diagnostics, dt and the final velocity fields."""
@@ -87,7 +90,7 @@ def gpu_leg(case, storage, steps, warmup):
     import paper_1911_12913_amd as t2s2
 
     torch.cuda.set_device(0)
-    ctx = t2s2.context_for_case(case, storage=storage, device="cuda:0")
+    ctx = t2s2.context_for_case(case, storage=storage, device="cuda:0", **overrides)
     ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
     ctx.step(warmup)
     torch.cuda.synchronize()
@@ -142,6 +145,9 @@ def main(argv=None):
     ap.add_argument("--cpu-threads", type=int, default=None)
     ap.add_argument("--cpu-single-steps", type=int, default=1,
                     help="oracle steps timed on one host thread (0 = skip)")
+    ap.add_argument("--t1s2-steps", type=int, default=None,
+                    help="steps of the FP64 T1S2 (A = 0) line at CFL 0.25 (default: --steps; "
+                         "0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed region, one plain device copy of this many bytes "
                          "(reference dispatch for scaling rocprofv3 memory counters)")
@@ -194,6 +200,24 @@ def main(argv=None):
         del vel_f
     del exact
 
+    t1s2 = None
+    t1s2_steps = args.steps if args.t1s2_steps is None else args.t1s2_steps
+    if t1s2_steps > 0:
+        case0 = tgv_case(n, nu, 0.25, eta)
+        ms_0, diag_0, dt_0, vel_0 = gpu_leg(case0, "f64", t1s2_steps, args.warmup, A=0.0)
+        v_0 = nodes * t1s2_steps / (ms_0 * 1e-3) / 1e6
+        _, ue0, ve0, _ = W_tgv_fields(case0, (args.warmup + t1s2_steps) * dt_0)
+        exact0 = torch.stack([torch.from_numpy(ue0), torch.from_numpy(ve0)]).to("cuda:0")
+        t1s2 = {"value": v_0, "unit": "MLUPS", "ms_per_step": ms_0 / t1s2_steps,
+                "steps": t1s2_steps, "scheme": "T1S2 (A = 0)", "storage": "f64", "cfl": 0.25,
+                "dt": dt_0, "kernel": "single_step_kernel",
+                "hbm_frac": BYTES_PER_NODE["f64"] * nodes / (ms_0 / t1s2_steps * 1e-3) / 1e9
+                / HBM_PEAK_GBS,
+                "t2s2_fdlbm1_step_time_ratio": ms_step / (ms_0 / t1s2_steps),
+                "rel_l2_velocity_vs_closed_form": rel_l2_dev(vel_0, exact0),
+                "nonfinite": diag_0["nonfinite"]}
+        del vel_0, exact0
+
     cpu = None
     if args.cpu_steps > 0:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
@@ -232,6 +256,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "rel_l2_velocity_vs_closed_form": gre,
         "precision_forms": forms,
+        "t1s2": t1s2,
         "diagnostics_after": {k: diag[k] for k in ("kinetic_energy", "max_speed", "nonfinite")},
     }
     print(json.dumps(rec), flush=True)

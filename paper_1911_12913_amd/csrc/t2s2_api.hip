@@ -117,6 +117,43 @@ bool check_axis(const double* c, int n, int per, double period, std::string& why
   return true;
 }
 
+// Strip plan of the step kernel that p selects: strips of 56 output columns
+// grouped into units of the kernel's strips per block.  The block count is
+// set at bind time (plan_blocks).
+void plan_strips(StepParams& p, int storage) {
+  p.nstrips = (p.nx + kStripOut - 1) / kStripOut;
+  const int spb = strips_per_block(storage, p.single ? 0 : p.scheme);
+  p.nunits = (p.nstrips + spb - 1) / spb;
+  p.nblocks = 8;
+  p.band = p.ny;
+}
+
+// One block per resident slot (CUs x blocks per CU), so every block runs in
+// a single wave of the grid with an equal share of the unit-rows (a unit is
+// the block's group of neighbouring strips), as long as a share keeps at
+// least 8 unit-rows.  Smaller meshes, where a block's march is a few
+// latency-bound iterations, use one block per CU (equal work on every CU)
+// while a share keeps at least 4 unit-rows, and below that one block per 4
+// unit-rows.  A multiple of 8 for the XCD-aware block order.  Returns the
+// grid size, or -1 if the kernel cannot be resident.
+int plan_blocks(StepParams& p, int storage, int cus) {
+  const bool walls = !p.per_x || !p.per_y;
+  const int per_cu = step_blocks_per_cu(storage, p.has_force != 0, walls, p.single ? 0 : p.scheme);
+  if (per_cu < 1) return -1;
+  const long long rows = static_cast<long long>(p.nunits) * p.ny;
+  const long long slots = static_cast<long long>(cus) * per_cu;
+  long long nb = rows >= 8 * slots ? slots : (rows >= 4LL * cus ? cus : rows / 4);
+  if (const char* env = std::getenv("T2S2_BLOCKS")) nb = std::atoll(env);
+  nb = std::max<long long>(8, nb / 8 * 8);
+  nb = std::min<long long>(nb, std::max<long long>(8, rows / 8 * 8));
+  p.nblocks = static_cast<int>(nb);
+  // Band height = one block's share, so that (away from the last band) each
+  // block owns exactly one unit of one band and the blocks of neighbouring
+  // units march the same rows at the same time.
+  p.band = static_cast<int>(std::min<long long>(p.ny, std::max<long long>(1, (rows + nb - 1) / nb)));
+  return static_cast<int>(nb);
+}
+
 }  // namespace
 
 struct t2s2_ctx {
@@ -137,6 +174,11 @@ struct t2s2_ctx {
   StepParams sp{};
   AuxParams ap{};
   int grid = 0;
+  // The two-stencil kernel's plan of the same step (its own occupancy), for
+  // the adjoint's recompute, which stores S, formed only by step_kernel;
+  // equal to sp unless sp.single.
+  StepParams sp_gen{};
+  int grid_gen = 0;
   // adjoint
   AdjParams adj{};
   bool adj_bound = false;
@@ -231,6 +273,8 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   const double w = c->omega, dt = c->dt;
   StepParams& p = c->sp;
   p.scheme = scheme;
+  // At A = 0 the half step is the identity and one stencil remains (T1S2).
+  p.single = (scheme == 1 && A == 0.0) ? 1 : 0;
   p.nx = nx;
   p.ny = ny;
   p.pitch = c->pitch;
@@ -302,14 +346,14 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   c->jx = measure(xs, cfg->periodic_x, cfg->period_x);
   c->jy = measure(ys, cfg->periodic_y, cfg->period_y);
 
-  // Launch plan: strips of kStripOut output columns; the block count is set
-  // at bind time from the device's CU count and the kernel's occupancy.
-  p.nstrips = (nx + kStripOut - 1) / kStripOut;
-  const int spb = strips_per_block(cfg->storage, scheme);
-  p.nunits = (p.nstrips + spb - 1) / spb;
-  p.nblocks = 8;
-  p.band = ny;
+  // Launch plans; the block counts are set at bind time from the device's
+  // CU count and the kernels' occupancy.
+  plan_strips(p, cfg->storage);
   c->grid = 8;
+  c->sp_gen = p;
+  c->sp_gen.single = 0;
+  plan_strips(c->sp_gen, cfg->storage);
+  c->grid_gen = 8;
 
   size_t off = 0;
   c->off_wx = off;
@@ -387,32 +431,18 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   c->sp.wy32 = reinterpret_cast<const float*>(c->ws + c->off_wy32);
   c->ap.jx = reinterpret_cast<const double*>(c->ws + c->off_jx);
   c->ap.jy = reinterpret_cast<const double*>(c->ws + c->off_jy);
-  // One block per resident slot (CUs x blocks per CU), so every block runs
-  // in a single wave of the grid with an equal share of the unit-rows (a
-  // unit is the block's group of neighbouring strips), as long as a share
-  // keeps at least 8 unit-rows.  Smaller meshes, where a block's march is a
-  // few latency-bound iterations, use one block per CU (equal work on every
-  // CU) while a share keeps at least 4 unit-rows, and below that one block
-  // per 4 unit-rows.  A multiple of 8 for the XCD-aware block order.
+  c->sp_gen.wx = c->sp.wx;
+  c->sp_gen.wy = c->sp.wy;
+  c->sp_gen.wx32 = c->sp.wx32;
+  c->sp_gen.wy32 = c->sp.wy32;
   int dev = 0, cus = 0;
   e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e, "bind: device query");
-  const bool walls = !c->sp.per_x || !c->sp.per_y;
-  int per_cu = step_blocks_per_cu(c->cfg.storage, c->sp.has_force != 0, walls, c->sp.scheme);
-  if (per_cu < 1) return fail(T2S2_ERR_HIP, "bind: step kernel cannot be resident");
-  const long long rows = static_cast<long long>(c->sp.nunits) * c->ny;
-  const long long slots = static_cast<long long>(cus) * per_cu;
-  long long nb = rows >= 8 * slots ? slots : (rows >= 4LL * cus ? cus : rows / 4);
-  if (const char* env = std::getenv("T2S2_BLOCKS")) nb = std::atoll(env);
-  nb = std::max<long long>(8, nb / 8 * 8);
-  nb = std::min<long long>(nb, std::max<long long>(8, rows / 8 * 8));
-  c->sp.nblocks = static_cast<int>(nb);
-  // Band height = one block's share, so that (away from the last band) each
-  // block owns exactly one unit of one band and the blocks of neighbouring
-  // units march the same rows at the same time.
-  c->sp.band = static_cast<int>(std::min<long long>(c->ny, std::max<long long>(1, (rows + nb - 1) / nb)));
-  c->grid = static_cast<int>(nb);
+  c->grid = plan_blocks(c->sp, c->cfg.storage, cus);
+  c->grid_gen = c->sp.single ? plan_blocks(c->sp_gen, c->cfg.storage, cus) : c->grid;
+  if (!c->sp.single) c->sp_gen = c->sp;
+  if (c->grid < 1 || c->grid_gen < 1) return fail(T2S2_ERR_HIP, "bind: step kernel cannot be resident");
   c->bound = true;
   c->cur = 0;
   c->steps = 0;
@@ -678,7 +708,7 @@ int t2s2_adjoint_step(t2s2_ctx* c, const void* state_n, const void* lam_np1, voi
   if (int rc = adj_ready(c)) return rc;
   if (!state_n || !lam_np1 || !lam_n || lam_np1 == lam_n)
     return fail(T2S2_ERR_INVALID_ARG, "need a state and two distinct adjoint buffers");
-  hipError_t e = launch_adjoint_step(c->cfg.storage, c->adj, c->sp, c->grid, state_n, lam_np1,
+  hipError_t e = launch_adjoint_step(c->cfg.storage, c->adj, c->sp_gen, c->grid_gen, state_n, lam_np1,
                                      lam_n, c->adj_partial, domega_accum, c->stream);
   if (e != hipSuccess) return hip_fail(e, "adjoint_step");
   return T2S2_OK;

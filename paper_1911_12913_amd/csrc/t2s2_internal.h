@@ -15,6 +15,15 @@ constexpr int kQ = 9;
 constexpr int kLanes = 64;
 constexpr int kHalo = 4;
 constexpr int kStripOut = kLanes - 2 * kHalo;
+// The single-stencil step that the scheme reduces to at A = 0 (Guo's T1S2,
+// Remark I: the half-step prediction is the identity) reaches 2 nodes along
+// each axis.  It keeps the 56-column strips (the FP64 row stores of a strip
+// then start on a 64-byte boundary and fill whole 64-byte segments; 60-column
+// strips measured 17% slower), but needs only 2 halo rows, and its LDS ring
+// holds 16 rows (rows p0..p0+3 written while rows p0-6..p0+1 are read, so one
+// barrier per iteration suffices).
+constexpr int kHalo1 = 2;
+constexpr int kRing1 = 16;
 // Rows advanced per iteration of the y-march = waves per block.
 constexpr int kRowsPerIter = 4;
 constexpr int kBlockThreads = kLanes * kRowsPerIter;
@@ -35,8 +44,10 @@ enum Storage { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3 };
 // still fit on a CU.  One otherwise: FP64 rings fit only once per CU in a
 // two-strip block, and a single block per CU stalls the whole CU at every
 // barrier; T2S2-FDLBM2's wider rings do not fit twice.
+// Scheme code 0 here is the single-stencil (A = 0) step, which takes two
+// strips per FP32 block as well.
 __host__ __device__ constexpr int strips_per_block(int storage, int scheme) {
-  return (scheme == 1 && storage == kF32) ? 2 : 1;
+  return ((scheme == 1 || scheme == 0) && storage == kF32) ? 2 : 1;
 }
 __host__ __device__ constexpr int step_threads(int storage, int scheme) {
   return kBlockThreads * strips_per_block(storage, scheme);
@@ -55,6 +66,7 @@ struct StepParams {
   int band;     // rows per band of the band-major strip-row order
   int scheme;   // 1: T2S2-FDLBM1 family (eq 2.23); 2: T2S2-FDLBM2 (eq 5.23);
                 // 3: the eq 2.13 family with gradient weights b
+  int single;   // scheme 1 at A = 0 (T1S2): the single-stencil kernel
   void* save_s; // adjoint recompute only: S in the arithmetic type, else NULL
   const double* wx;   // [nx][2][4] dt-scaled x weights (FP64)
   const double* wy;   // [ny][2][4]
@@ -132,7 +144,8 @@ constexpr int kDiagSlots = 8;
 // Launchers (t2s2_kernels.hip).  Return hipError_t of the launch.
 hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s);
 hipError_t launch_step_save_s(int storage, const StepParams& p, int grid, hipStream_t s);
-// Resident step-kernel blocks per CU for this variant (-1 on error).
+// Resident step-kernel blocks per CU for this variant (-1 on error); scheme
+// 0 is the single-stencil (A = 0) kernel.
 int step_blocks_per_cu(int storage, bool force, bool walls, int scheme);
 hipError_t launch_init_macro(int storage, const AuxParams& a, void* state, const double* rho,
                              const double* ux, const double* uy, const double* grad,

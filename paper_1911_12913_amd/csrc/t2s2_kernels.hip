@@ -244,8 +244,11 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
     // iterations of loads are in flight while the stencil phases compute.
     Store gA[kQ], gB[kQ];
     const int pitch = static_cast<int>(p.pitch);
+    // Rows y0-4 .. y1+3 are needed; prefetches past the last one repeat it
+    // (found in cache instead of fetched from HBM).
     auto load_row = [&](int pr, Store (&gb)[kQ]) {
-      const int prm = p.per_y ? wrap_near(pr, ny) : clampi(pr, 0, ny - 1);
+      const int pc = min(pr, y1 + kHalo - 1);
+      const int prm = p.per_y ? wrap_near(pc, ny) : clampi(pc, 0, ny - 1);
       const unsigned boff =
           (static_cast<unsigned>(prm) * static_cast<unsigned>(pitch) + static_cast<unsigned>(cm)) *
           static_cast<unsigned>(sizeof(Store));
@@ -481,6 +484,230 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
       iteration(it + 1, gB, qB, qA);
     }
     __syncthreads();  // the next piece reuses the rings
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Single-stencil step: the scheme at A = 0, Guo's T1S2-FDLBM (Remark I).
+// With h = 0 the half-step prediction is the identity (S = P) and the mid-step
+// map returns its input (R = S), so the step is
+//   f~^{n+1} = Q - dt xi . grad_m R,  R = P = [2 f~ + w f^eq + dt F] / (2 + w),
+// R being the physical f^n (eqs 2.18-2.20).  R is pointwise, so one pass
+// forms R and Q of a row, puts R in an LDS ring, and takes the stencil of the
+// row four above.  Strips are those of step_kernel (56 outputs; the stencil
+// uses 2 of the 4 halo columns each side), marched from 2 rows above the
+// piece instead of 4.  Wall nodes of R take eq 3.10 from their
+// nearest interior node, written by that node's lane; the new state's wall
+// nodes are set by wall_fixup_kernel, as for step_kernel.  Each output takes
+// the same expressions in the same order as step_kernel at A = 0 (where
+// S = P + 0 L(P) and R = 1 S + 0 E reproduce P).
+//
+// Ring hazards, with rows p0..p0+3 loaded in an iteration and one barrier per
+// iteration between its two phases: phase 1 writes rows p0..p0+3 and, for
+// eq 3.10, wall rows p0-1 and p0+4; phase 2 reads rows p0-6..p0+1.  Over 16
+// slots the rows written in phase 1 of the next iteration (p0+3..p0+8) share
+// no slot with the rows still being read in phase 2 of this one.
+// ---------------------------------------------------------------------------
+template <typename Store, bool kForce, bool kWalls>
+__global__ __launch_bounds__(step_threads(kStorageOf<Store>, 0), (kMinWaves<Store, kForce, kWalls, 1>)) void single_step_kernel(
+    StepParams p) {
+  using Real = typename Cvt<Store>::R;
+  constexpr int kSB = strips_per_block(kStorageOf<Store>, 0);
+  constexpr int kThreads = step_threads(kStorageOf<Store>, 0);
+  constexpr int kSizeR = kRing1 * (kQ - 1) * kLanes;
+  __shared__ Real ringR_all[kSB * kSizeR];  // per strip: [slot][q-1][lane]
+
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+  const int half = kSB == 1 ? 0 : wave / kRowsPerIter;
+  const int t = kSB == 1 ? wave : wave % kRowsPerIter;
+  Real* const ringR = ringR_all + half * kSizeR;
+  const int nx = p.nx, ny = p.ny;
+  const Store* __restrict__ src = static_cast<const Store*>(p.src);
+  Store* __restrict__ dst = static_cast<Store*>(p.dst);
+  const long long plane = p.plane;
+
+  for (int i = threadIdx.x; i < kSB * kSizeR; i += kThreads) ringR_all[i] = Real(0);
+
+  // Work order and XCD-aware block map as in step_kernel.
+  const int G = gridDim.x;
+  const int L = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
+  if (L >= p.nblocks) return;  // padding block: whole block, before any barrier
+  const long long total = static_cast<long long>(p.nunits) * ny;
+  const long long band_pieces = static_cast<long long>(p.nunits) * p.band;
+  long long beg = total * L / p.nblocks;
+  const long long end = total * (L + 1) / p.nblocks;
+
+  while (beg < end) {  // uniform per block
+    const int b = static_cast<int>(beg / band_pieces);
+    const long long rem = beg - b * band_pieces;
+    const int r0 = b * p.band;
+    const int hb = min(p.band, ny - r0);
+    const int strip = static_cast<int>(rem / hb) * kSB + half;
+    const int y0 = r0 + static_cast<int>(rem % hb);
+    const int y1 = static_cast<int>(min(static_cast<long long>(r0 + hb), y0 + (end - beg)));
+    beg += y1 - y0;
+
+    const int x0 = strip * kStripOut;
+    const int x1 = min(x0 + kStripOut, nx);
+    const int c = x0 - kHalo + lane;
+    const int cm = p.per_x ? wrap(c, nx) : clampi(c, 0, nx - 1);
+    Real wxr[kWeightsPerNode];
+    {
+      const Real* wx = weights_x<Real>(p);
+#pragma unroll
+      for (int k = 0; k < kWeightsPerNode; ++k) wxr[k] = wx[cm * kWeightsPerNode + k];
+    }
+    const bool col_interior = p.per_x || (c >= 1 && c <= nx - 2);
+    const bool lane_o = lane >= kHalo && lane < kLanes - kHalo && c < x1;
+    const bool src_xl = !p.per_x && c == 1;
+    const bool src_xr = !p.per_x && c == nx - 2;
+
+    Real qA[kQ], qB[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) qA[q] = qB[q] = Real(0);
+
+    // Rows y0-2 .. y1+1 are needed, four per iteration from ybase = y0 - 2;
+    // iteration it outputs the rows loaded in iteration it - 1 (so Q stays
+    // in the registers of the wave that formed it).  Prefetches past the
+    // last needed row repeat that row, which the cache still holds.
+    const int ybase = y0 - kHalo1;
+    const int ylast = y1 + kHalo1 - 1;
+    const int niter = ((y1 - y0 + 1) / kRowsPerIter + 3) & ~1;
+
+    Store gA[kQ], gB[kQ];
+    const int pitch = static_cast<int>(p.pitch);
+    auto load_row = [&](int pr, Store (&gb)[kQ]) {
+      const int pc = min(pr, ylast);
+      const int prm = p.per_y ? wrap_near(pc, ny) : clampi(pc, 0, ny - 1);
+      const unsigned boff =
+          (static_cast<unsigned>(prm) * static_cast<unsigned>(pitch) + static_cast<unsigned>(cm)) *
+          static_cast<unsigned>(sizeof(Store));
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) gb[q] = *at_byte(src + q * plane, boff);
+    };
+    load_row(ybase + t, gA);
+    load_row(ybase + kRowsPerIter + t, gB);
+    __syncthreads();  // ring zero-fill / previous piece complete
+
+    auto iteration = [&](const int it, Store (&gb)[kQ], Real (&qnew)[kQ], const Real (&qold)[kQ]) {
+      const int p0 = ybase + kRowsPerIter * it;
+
+      // ---- phase 1: R (to LDS) and Q (registers) of row p0 + t.
+      {
+        const int pr = p0 + t;
+        Real g[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) g[q] = Cvt<Store>::ld(gb[q]);
+        load_row(pr + 2 * kRowsPerIter, gb);
+        double s, jx, jy;
+        moment_sums(g, s, jx, jy);
+        Real rho, ux, uy;
+        velocity(s, jx, jy, rho, ux, uy);
+        if (kForce) {
+          ux += static_cast<Real>(p.half_dt * p.Fx);
+          uy += static_cast<Real>(p.half_dt * p.Fy);
+        }
+        const Real d = static_cast<Real>(s);
+        Real X[kQ];
+        eq_brackets(ux, uy, X);
+        const auto& k = coef<Real>(p);
+        Real R[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          const Real E = d + rho * X[q];
+          Real Rq = k.cPg * g[q] + k.kP[wclass(q)] * E;
+          Real Qq = k.cQg * g[q] + k.kQ[wclass(q)] * E;
+          if (kForce) {
+            const Real Fq = force_term(q, p, ux, uy, E);
+            Rq += static_cast<Real>(p.cPF) * Fq;
+            Qq += static_cast<Real>(p.cQF) * Fq;
+          }
+          R[q] = Rq;
+          qnew[q] = Qq;
+        }
+        const bool row_int = p.per_y || (pr >= 1 && pr <= ny - 2);
+        if (row_int && col_interior) {
+          Real* slot = ringR + (pr & (kRing1 - 1)) * (kQ - 1) * kLanes;
+#pragma unroll
+          for (int q = 1; q < kQ; ++q) slot[(q - 1) * kLanes + lane] = R[q];
+          // Wall nodes whose nearest interior node is this one (eq 3.10;
+          // corners take the diagonal neighbour), from the moments of R.
+          const bool src_yb = !p.per_y && pr == 1;
+          const bool src_yt = !p.per_y && pr == ny - 2;
+          if (kWalls && (src_xl || src_xr || src_yb || src_yt)) {
+            double s2, jx2, jy2;
+            moment_sums(R, s2, jx2, jy2);
+            Real rho2, ux2, uy2;
+            velocity(s2, jx2, jy2, rho2, ux2, uy2);
+            for (int dy = -1; dy <= 1; ++dy) {
+              if ((dy == -1 && !src_yb) || (dy == 1 && !src_yt)) continue;
+              for (int dx = -1; dx <= 1; ++dx) {
+                if ((dx == -1 && !src_xl) || (dx == 1 && !src_xr)) continue;
+                if (dx == 0 && dy == 0) continue;
+                // A source in the strip's edge lane has its wall node outside
+                // the strip; no output of this strip reads it.
+                if (lane + dx < 0 || lane + dx >= kLanes) continue;
+                double ub, vb;
+                wall_velocity(p, c + dx, pr + dy, ub, vb);
+                Real sh[kQ];
+                nee_shift(static_cast<double>(rho2), static_cast<double>(ux2),
+                          static_cast<double>(uy2), ub, vb, sh);
+                Real* slotW = ringR + ((pr + dy) & (kRing1 - 1)) * (kQ - 1) * kLanes;
+#pragma unroll
+                for (int q = 1; q < kQ; ++q) slotW[(q - 1) * kLanes + lane + dx] = R[q] + sh[q];
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+
+      // ---- phase 2: f~^{n+1} of row p0 - 4 + t (whole wave computes,
+      // interior output lanes store).
+      {
+        const int o = p0 - kRowsPerIter + t;
+        const bool row_ok = o >= y0 && o < y1 && (p.per_y || (o >= 1 && o <= ny - 2));
+        if (row_ok) {
+          Real wyr[kWeightsPerNode];
+          row_weights(weights_y<Real>(p), o, wyr);
+          const Real* rb[5];
+#pragma unroll
+          for (int k = 0; k < 5; ++k)
+            rb[k] = ringR + ((o + k - 2) & (kRing1 - 1)) * (kQ - 1) * kLanes + lane;
+          Real out[kQ];
+          out[0] = qold[0];
+#pragma unroll
+          for (int q = 1; q < kQ; ++q) {
+            const int pq = (q - 1) * kLanes;
+            const Real centre = rb[2][pq];
+            Real acc = qold[q];
+            if (ex_of(q) > 0) acc = x_taps<0>(wxr, centre, acc);
+            if (ex_of(q) < 0) acc = x_taps<1>(wxr, centre, acc);
+            if (ey_of(q) != 0) {
+              const int sy = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+              for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][pq];
+            }
+            out[q] = acc;
+          }
+          if (lane_o && col_interior) {
+            const unsigned boff =
+                (static_cast<unsigned>(o) * static_cast<unsigned>(pitch) + static_cast<unsigned>(c)) *
+                static_cast<unsigned>(sizeof(Store));
+#pragma unroll
+            for (int q = 0; q < kQ; ++q)
+              store_state(at_byte(dst + q * plane, boff), Cvt<Store>::st(out[q]));
+          }
+        }
+      }
+    };
+
+    for (int it = 0; it < niter; it += 2) {
+      iteration(it, gA, qA, qB);
+      iteration(it + 1, gB, qB, qA);
+    }
+    __syncthreads();  // the next piece reuses the ring
   }
 }
 
@@ -738,10 +965,27 @@ void launch_fused(const StepParams& p, dim3 g, dim3 b, hipStream_t s, bool walls
 }
 
 template <typename Store>
+void launch_single(const StepParams& p, dim3 g, dim3 b, hipStream_t s, bool walls) {
+  if (p.has_force) {
+    if (walls)
+      hipLaunchKernelGGL((single_step_kernel<Store, true, true>), g, b, 0, s, p);
+    else
+      hipLaunchKernelGGL((single_step_kernel<Store, true, false>), g, b, 0, s, p);
+  } else {
+    if (walls)
+      hipLaunchKernelGGL((single_step_kernel<Store, false, true>), g, b, 0, s, p);
+    else
+      hipLaunchKernelGGL((single_step_kernel<Store, false, false>), g, b, 0, s, p);
+  }
+}
+
+template <typename Store>
 hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
-  const dim3 g(grid), b(step_threads(kStorageOf<Store>, p.scheme));
+  const dim3 g(grid), b(step_threads(kStorageOf<Store>, p.single ? 0 : p.scheme));
   const bool walls = !p.per_x || !p.per_y;
-  if (p.scheme == 2)
+  if (p.single)
+    launch_single<Store>(p, g, b, s, walls);
+  else if (p.scheme == 2)
     launch_fused<Store, 2>(p, g, b, s, walls);
   else if (p.scheme == 3)
     launch_fused<Store, 3>(p, g, b, s, walls);
@@ -800,7 +1044,22 @@ int occupancy_s(bool force, bool walls) {
 }
 
 template <typename Store>
+int occupancy_single(bool force, bool walls) {
+  int n = 0;
+  const int threads = step_threads(kStorageOf<Store>, 0);
+  hipError_t e;
+  if (force)
+    e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, single_step_kernel<Store, true, true>, threads, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, single_step_kernel<Store, true, false>, threads, 0);
+  else
+    e = walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, single_step_kernel<Store, false, true>, threads, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, single_step_kernel<Store, false, false>, threads, 0);
+  return e == hipSuccess ? n : -1;
+}
+
+template <typename Store>
 int occupancy_t(bool force, bool walls, int scheme) {
+  if (scheme == 0) return occupancy_single<Store>(force, walls);
   if (scheme == 2) return occupancy_s<Store, 2>(force, walls);
   if (scheme == 3) return occupancy_s<Store, 3>(force, walls);
   return occupancy_s<Store, 1>(force, walls);
@@ -835,7 +1094,7 @@ hipError_t launch_step_save_s_t(const StepParams& p, int grid, hipStream_t s) {
 }
 
 hipError_t launch_step_save_s(int storage, const StepParams& p, int grid, hipStream_t s) {
-  if (p.has_force || p.scheme != 1 || !p.save_s) return hipErrorInvalidValue;
+  if (p.has_force || p.scheme != 1 || p.single || !p.save_s) return hipErrorInvalidValue;
   T2S2_DISPATCH(storage, return launch_step_save_s_t<Store>(p, grid, s));
   return hipSuccess;
 }

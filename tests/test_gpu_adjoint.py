@@ -29,12 +29,17 @@ def _dev(a):
     return torch.as_tensor(np.asarray(a), dtype=torch.float64, device="cuda:0")
 
 
-@pytest.mark.parametrize("kind", ["cavity", "tgv"])
+@pytest.mark.parametrize("kind", ["cavity", "tgv", "cavity_t1s2"])
 def test_adjoint_step_dot_product(kind):
     """<J v, w> = <v, J^T w> for one step: J v by central differences of the
-    GPU step, J^T w by the hand-written adjoint step."""
+    GPU step, J^T w by the hand-written adjoint step.  At A = 0 the step runs
+    the single-stencil kernel and the adjoint's recompute the two-stencil
+    one, so the test also ties the two forward kernels together."""
     if kind == "cavity":
         case = W.cavity_case(40, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=1e-3, seed=1)
+    elif kind == "cavity_t1s2":
+        case = W.cavity_case(40, lid=0.1, re=400.0, cfl=0.25, eta=0.1, noise=1e-3, seed=1)
+        case.A = 0.0
     else:
         case = W.tgv_case(48, 40, u0=0.05, nu=0.01, cfl=0.6, eta=0.05)
     print(f"[gpu] adjoint dot product {kind}", flush=True)

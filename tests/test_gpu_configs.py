@@ -107,6 +107,36 @@ def test_tgv4096_scheme_throughput(storage, monkeypatch):
         torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_tgv4096_t1s2_vs_t2s2_step_time(storage, monkeypatch):
+    """Step time of Guo's T1S2 (A = 0, the single-stencil kernel) against
+    T2S2-FDLBM1 (A = 1/2, two stencils) on the 4096^2 Taylor-Green grid at
+    CFL 0.25 (T1S2's stable range), 100 steps each after 10 warm-up steps;
+    the cost ratio is reported (Table 4 of the paper implies about 1.9 on its
+    CPU code)."""
+    monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+    case = W.tgv_case(4096, 4096, u0=0.01, nu=1e-4, cfl=0.25, eta=0.01)
+    us = {}
+    for A in (0.0, 0.5):
+        ctx = t2s2.context_for_case(case, storage=storage, A=A)
+        ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
+        ctx.step(10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.step(100)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        us[A] = e0.elapsed_time(e1) / 100 * 1e3
+        d = ctx.diagnostics()
+        _say(f"    tgv4096 {storage} A = {A}: {us[A]:.1f} us/step, "
+             f"{case.nx * case.ny / us[A]:.0f} MLUPS, max|u| {d['max_speed']:.6e}")
+        assert 0.0 < d["max_speed"] <= 0.01
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    _say(f"    tgv4096 {storage}: T2S2-FDLBM1 / T1S2 step-time ratio {us[0.5] / us[0.0]:.3f}")
+
+
 def _cavity257():
     return W.cavity_case(256, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
 
@@ -131,12 +161,13 @@ def test_cavity257_5000_steps_matches_oracle():
 
 
 @pytest.mark.parametrize("kind,scheme", [("cavity65", 1), ("tgv48x40", 1), ("cavity65", 2),
-                                         ("cavity65", 3)])
+                                         ("cavity65", 3), ("cavity65", 0)])
 def test_graph_stepping_is_bitwise_plain_stepping(kind, scheme):
     """A captured multi-step HIP graph gives bitwise the state of plain
     launches, replay after replay, with plain steps and host synchronisation
     between the replays (which also leave the state in the other buffer);
-    for each scheme (the family with B~ = (1/4, 1/2, 1/4))."""
+    for each scheme (the family with B~ = (1/4, 1/2, 1/4); "scheme 0" is
+    T2S2-FDLBM1 at A = 0, the single-stencil kernel)."""
     if kind == "cavity65":
         case = W.cavity_case(64, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
     else:
@@ -144,6 +175,9 @@ def test_graph_stepping_is_bitwise_plain_stepping(kind, scheme):
     phi0 = oracle.init(case)
     _say(f"[gpu] graph stepping {kind} scheme {scheme}")
     kw = dict(scheme=scheme, btilde=(0.25, 0.5, 0.25)) if scheme == 3 else dict(scheme=scheme)
+    if scheme == 0:
+        case.cfl = 0.25
+        kw = dict(scheme=1, A=0.0)
     s_plain, s_graph = torch.cuda.Stream(), torch.cuda.Stream()
     a = t2s2.context_for_case(case, stream=s_plain, **kw)
     b = t2s2.context_for_case(case, stream=s_graph, **kw)

@@ -495,3 +495,88 @@ def test_largest_mesh_uniform_flow_is_a_fixed_point():
     ctx.close()
     del ctx, d, u, v
     torch.cuda.empty_cache()
+
+
+# ------------------- the single-stencil step at A = 0 (Guo's T1S2-FDLBM)
+
+def _t1s2_case(kind):
+    if kind == "tgv150x70":
+        case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.25, eta=0.05, A=0.0)
+        return case, oracle.init(case) + W.random_state((9, 70, 150), 1e-5, 8)
+    if kind == "cavity130x65":
+        case = _ragged_cavity(0.25)
+    elif kind == "poiseuille":
+        case = W.poiseuille_case(dt_over_y1=0.25, eta=0.1)
+    else:
+        case = W.cavity_case(4, lid=0.1, re=100.0, cfl=0.25, eta=0.1, noise=1e-4, seed=5)
+    case.A = 0.0
+    return case, oracle.init(case)
+
+
+@pytest.mark.parametrize("kind", ["tgv150x70", "cavity130x65", "poiseuille", "cavity5x5"])
+def test_t1s2_single_stencil_matches_oracle(kind):
+    """At A = 0 the library runs the single-stencil kernel (2 halo rows, a
+    16-row ring, one barrier per iteration): periodic Taylor-Green across the
+    seams, the ragged walled cavity (three strips, 56 + 56 + 18 columns), the
+    forced channel (x period of 10 columns) and the 5 x 5 cavity, 150 steps at
+    CFL 0.25, against the oracle's A = 0 march."""
+    case, phi0 = _t1s2_case(kind)
+    ref = oracle.run(case, phi0, 150, A=0.0)
+    _, g, d, u, v = _gpu_run(case, phi0, 150, A=0.0)
+    _compare(case, g, d, u, v, ref)
+
+
+@pytest.mark.parametrize("blocks", ["8", "16", "24", "40", "48", "64"])
+def test_t1s2_walled_ragged_tiles(blocks, monkeypatch):
+    """The ragged walled cavity at A = 0 cut into 8 to 64 block ranges, so
+    pieces start at every row residue and the wall rows' extrapolated R is
+    written from either neighbouring iteration."""
+    monkeypatch.setenv("T2S2_BLOCKS", blocks)
+    case, phi0 = _t1s2_case("cavity130x65")
+    ref = oracle.run(case, phi0, 120, A=0.0)
+    _, g, d, u, v = _gpu_run(case, phi0, 120, A=0.0)
+    _compare(case, g, d, u, v, ref)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
+def test_t1s2_single_stencil_equals_two_stencil_kernel(storage):
+    """The single-stencil kernel against the two-stencil kernel at A = 0 (run
+    as the family with B~ = (0, 1, 0), which is the T2S2-FDLBM1 kernel bit
+    for bit): the same expressions in the same order, so the states agree to
+    rounding (reported: bitwise or not) on the walled cavity, every storage."""
+    case, phi0 = _t1s2_case("cavity130x65")
+    _, g1, *_ = _gpu_run(case, phi0, 80, storage=storage, A=0.0)
+    _, g3, *_ = _gpu_run(case, phi0, 80, storage=storage, A=0.0, scheme=3,
+                         btilde=(0.0, 1.0, 0.0))
+    e = _rel(g1, g3)
+    print(f"    {storage}: single vs two-stencil rel L2 {e:.3e}, bitwise "
+          f"{np.array_equal(g1, g3)}", flush=True)
+    assert e <= (1e-15 if storage == "f64" else 1e-6)
+
+
+def test_t1s2_tiling_invariance_bitwise(monkeypatch):
+    """Single-stencil kernel: bitwise the same state for three block counts,
+    FP64 walled and FP32 periodic (two strips per block)."""
+    cav = W.cavity_case(96, lid=0.1, re=1000.0, cfl=0.25, eta=0.1, noise=1e-6, seed=0)
+    cav.A = 0.0
+    tgv, phi_t = _t1s2_case("tgv150x70")
+    for case, phi0, storage in ((cav, oracle.init(cav), "f64"), (tgv, phi_t, "f32")):
+        outs = []
+        for blocks in ("8", "40", "96"):
+            monkeypatch.setenv("T2S2_BLOCKS", blocks)
+            _, g, *_ = _gpu_run(case, phi0, 64, storage=storage, A=0.0)
+            outs.append(g)
+        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_t1s2_fp32_error_vs_oracle():
+    """The single-stencil kernel with FP32 deviation storage: velocity error
+    against the FP64 oracle's A = 0 march, reported and bounded."""
+    case = W.tgv_case(64, 64, u0=0.01, nu=0.01, cfl=0.25, eta=0.01, A=0.0)
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 400, A=0.0)
+    _, g, d, u, v = _gpu_run(case, phi0, 400, storage="f32", A=0.0)
+    _, ur, vr = oracle.moments(case, ref)
+    err = _rel(np.stack([u, v]), np.stack([ur, vr]))
+    print(f"    f32 T1S2: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
+    assert err <= 3e-5
