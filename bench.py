@@ -17,7 +17,10 @@ forms (deviations stored in FP32, BF16 or FP16, FP32 arithmetic, FP64
 moment sums) then run the same steps on the same grid; each reports its
 MLUPS, its speed-up over the FP64 line and the relative L2 error of its
 final velocity field against the FP64 result (which matches the oracle to
-round-off) and against the closed-form decay of eq 3.4.  Guo's T1S2-FDLBM
+round-off) and against the closed-form decay of eq 3.4.  A plain copy of
+the nine planes with the step's store policy, over buffers of the state's
+size, gives the practical bandwidth ceiling beside the published peak.
+Guo's T1S2-FDLBM
 (A = 0, the single-stencil kernel) runs last on the same grid in FP64 at
 CFL 0.25, inside its stable range, for the cost of one scheme against the
 other.
@@ -108,6 +111,33 @@ def gpu_leg(case, storage, steps, warmup, **overrides):
     dt = ctx.dt
     ctx.close()
     return ms, diag, dt, torch.stack([ux, uy])
+
+
+def copy_ceiling(n, elem_bytes, reps=20, warmup=3):
+    """Bandwidth of the reference nine-plane copy (t2s2_copy_probe) over
+    buffers of the state's size, timed with HIP events on its stream."""
+    import torch
+
+    import paper_1911_12913_amd as t2s2
+
+    dt = {8: torch.float64, 4: torch.float32, 2: torch.float16}[elem_bytes]
+    src = torch.ones(9 * n, dtype=dt, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.Stream()
+    for _ in range(warmup):
+        t2s2.copy_probe(src, dst, stream=stream)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        t2s2.copy_probe(src, dst, stream=stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * 9 * n * elem_bytes / (ms * 1e-3) / 1e9
 
 
 def rel_l2_dev(a, b) -> float:
@@ -218,6 +248,14 @@ def main(argv=None):
                 "nonfinite": diag_0["nonfinite"]}
         del vel_0, exact0
 
+    ceiling = {}
+    for st in dict.fromkeys([args.storage, "f32"]):
+        eb = BYTES_PER_NODE[st] // 18
+        gbs = copy_ceiling(nodes, eb)
+        ceiling[st] = {"value": gbs, "unit": "GB/s", "frac_of_peak": gbs / HBM_PEAK_GBS,
+                       "kernel": "copy_planes_kernel", "elem_bytes": eb}
+    ceiling[args.storage]["step_frac_of_ceiling"] = achieved / ceiling[args.storage]["value"]
+
     cpu = None
     if args.cpu_steps > 0:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
@@ -253,6 +291,7 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "step_kernel", "bytes_per_node": BYTES_PER_NODE[args.storage]},
+        "copy_ceiling": ceiling,
         "cpu_baseline": cpu,
         "rel_l2_velocity_vs_closed_form": gre,
         "precision_forms": forms,

@@ -284,6 +284,20 @@ typedef struct t2s2_stability_params {
 int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, const double* r,
                        int npoints, double* radius, void* stream);
 
+/* Reference copy for the step's roofline (not part of the method): copies
+ * the nine planes of plane_elems elements of elem_bytes (8, 4 or 2) bytes
+ * each, [9][plane_elems], from src to dst (device pointers, aligned to
+ * elem_bytes, not overlapping), bit for bit, one element per lane and plane,
+ * with the step kernel's store policy (non-temporal for 8-byte elements).
+ * Its bandwidth, 2 * 9 * plane_elems * elem_bytes bytes per call, is the
+ * practical ceiling of a kernel that reads and writes the state once.
+ * Asynchronous on `stream` (a hipStream_t, NULL = default); allocates
+ * nothing.  INVALID_ARG for NULL, misaligned or overlapping buffers, a
+ * non-positive plane_elems or another elem_bytes; HIP_ERROR if the launch
+ * fails. */
+int t2s2_copy_probe(const void* src, void* dst, int64_t plane_elems, int elem_bytes,
+                    void* stream);
+
 void t2s2_destroy(t2s2_ctx* ctx);
 
 /* Message of the last failing call on this thread ("" if none). */

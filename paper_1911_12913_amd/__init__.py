@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
         "t2s2_adjoint_read": (i, [vp, vp, vp]),
         "t2s2_adjoint_load": (i, [vp, vp, vp]),
         "t2s2_stability_map": (i, [ctypes.POINTER(StabilityParams), vp, vp, i, vp, vp]),
+        "t2s2_copy_probe": (i, [vp, vp, i64, i, vp]),
         "t2s2_destroy": (None, [vp]),
         "t2s2_last_error": (ctypes.c_char_p, []),
     }
@@ -136,7 +137,8 @@ def exported_symbols() -> Sequence[str]:
             "t2s2_diagnostics", "t2s2_velocity_error", "t2s2_stencil_weights", "t2s2_omega", "t2s2_adjoint_state_bytes",
             "t2s2_adjoint_scratch_bytes", "t2s2_bind_adjoint", "t2s2_adjoint_seed_velocity",
             "t2s2_adjoint_step", "t2s2_adjoint_init_macro", "t2s2_adjoint_read",
-            "t2s2_adjoint_load", "t2s2_stability_map", "t2s2_destroy", "t2s2_last_error")
+            "t2s2_adjoint_load", "t2s2_stability_map", "t2s2_copy_probe", "t2s2_destroy",
+            "t2s2_last_error")
 
 
 def _check(rc: int):
@@ -405,3 +407,20 @@ def stability_map(model, omega, r, *, eta, u=(0.0, 0.0), A=0.5, b2bar=0.5, b2til
         _check(lib.t2s2_stability_map(ctypes.byref(prm), w.data_ptr(), rr.data_ptr(), w.numel(),
                                       out.data_ptr(), st.cuda_stream))
     return out
+
+
+def copy_probe(src, dst, stream=None):
+    """Reference copy of a nine-plane state (t2s2_copy_probe): `src` and
+    `dst` are device tensors of the same dtype (8, 4 or 2 bytes per element)
+    and a number of elements divisible by 9; asynchronous on `stream`."""
+    import torch
+
+    lib = load_library()
+    if src.dtype != dst.dtype or src.numel() != dst.numel() or src.numel() % 9:
+        raise ValueError("src and dst: same dtype and size, a multiple of 9 elements")
+    if not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous")
+    with torch.cuda.device(src.device):
+        st = stream if stream is not None else torch.cuda.current_stream(src.device)
+        _check(lib.t2s2_copy_probe(src.data_ptr(), dst.data_ptr(), src.numel() // 9,
+                                   src.element_size(), st.cuda_stream))

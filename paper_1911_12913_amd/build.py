@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libt2s2.so")
-SOURCES = ["t2s2_kernels.hip", "t2s2_adjoint.hip", "t2s2_stability.hip", "t2s2_api.hip"]
+SOURCES = ["t2s2_kernels.hip", "t2s2_adjoint.hip", "t2s2_stability.hip", "t2s2_probe.hip",
+           "t2s2_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

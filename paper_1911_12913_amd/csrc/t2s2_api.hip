@@ -745,6 +745,26 @@ int t2s2_adjoint_load(t2s2_ctx* c, const double* in, void* lam) {
   return T2S2_OK;
 }
 
+int t2s2_copy_probe(const void* src, void* dst, int64_t plane_elems, int elem_bytes,
+                    void* stream) {
+  g_last_error.clear();
+  if (!src || !dst) return fail(T2S2_ERR_INVALID_ARG, "NULL buffer");
+  if (plane_elems <= 0) return fail(T2S2_ERR_INVALID_ARG, "plane_elems must be > 0");
+  if (elem_bytes != 8 && elem_bytes != 4 && elem_bytes != 2)
+    return fail(T2S2_ERR_INVALID_ARG, "elem_bytes must be 8, 4 or 2");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) %
+      static_cast<uintptr_t>(elem_bytes))
+    return fail(T2S2_ERR_INVALID_ARG, "buffers must be aligned to elem_bytes");
+  const uintptr_t bytes = static_cast<uintptr_t>(kQ) * static_cast<uintptr_t>(plane_elems) *
+                          static_cast<uintptr_t>(elem_bytes);
+  const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+  if (a < b + bytes && b < a + bytes) return fail(T2S2_ERR_INVALID_ARG, "buffers overlap");
+  hipError_t e = launch_copy_probe(src, dst, static_cast<long long>(plane_elems), elem_bytes,
+                                   static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "copy_probe");
+  return T2S2_OK;
+}
+
 int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, const double* r,
                        int npoints, double* radius, void* stream) {
   g_last_error.clear();

@@ -164,6 +164,11 @@ hipError_t launch_velocity_error(int storage, const AuxParams& a, const void* st
 
 size_t storage_bytes(int storage);
 
+// Reference copy of nine planes of `plane` elements of elem_bytes (8, 4 or
+// 2) bytes (t2s2_probe.hip).
+hipError_t launch_copy_probe(const void* src, void* dst, long long plane, int elem_bytes,
+                             hipStream_t s);
+
 // Adjoint launchers (t2s2_adjoint.hip).
 size_t adjoint_real_bytes(int storage);
 hipError_t launch_adjoint_step(int storage, const AdjParams& a, const StepParams& sp,

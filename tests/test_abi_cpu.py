@@ -173,3 +173,21 @@ def test_stability_map_argument_checks_without_device():
     fam.btilde[1] = 0.5   # valid: fails only on the NULL arrays
     assert lib.t2s2_stability_map(ctypes.byref(fam), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
     assert lib.t2s2_stability_map(ctypes.byref(fam), None, None, 0, None, None) == t2s2.OK
+
+
+def test_copy_probe_argument_checks_without_device():
+    """The reference copy refuses NULL, misaligned and overlapping buffers,
+    empty planes and other element sizes before any device call."""
+    lib = t2s2.load_library()
+    a, b = 1 << 20, 1 << 30   # addresses never dereferenced: every call fails its checks
+    bad = t2s2.ERR_INVALID_ARG
+    assert lib.t2s2_copy_probe(None, b, 16, 8, None) == bad
+    assert lib.t2s2_copy_probe(a, None, 16, 8, None) == bad
+    assert lib.t2s2_copy_probe(a, b, 0, 8, None) == bad
+    assert lib.t2s2_copy_probe(a, b, -5, 8, None) == bad
+    assert lib.t2s2_copy_probe(a, b, 16, 3, None) == bad
+    assert lib.t2s2_copy_probe(a, b, 16, 16, None) == bad
+    assert lib.t2s2_copy_probe(a + 4, b, 16, 8, None) == bad
+    assert lib.t2s2_copy_probe(a, a + 9 * 16 * 8 - 8, 16, 8, None) == bad   # overlap
+    assert lib.t2s2_copy_probe(a + 9 * 16 * 8 - 8, a, 16, 8, None) == bad
+    assert b"overlap" in lib.t2s2_last_error()

@@ -270,3 +270,18 @@ def test_cavity2049_precision_forms_after_20000_steps():
         e = _rel(vel[storage], vel["f64"])
         _say(f"    {storage}: velocity rel L2 vs FP64 after 20000 steps {e:.3e}")
         assert e <= bound
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32", "float16"])
+def test_copy_probe_is_a_bitwise_copy(dtype):
+    """The reference copy kernel of the roofline copies all nine planes bit
+    for bit (a ragged plane of 1000 elements, not a multiple of the block)."""
+    dt = getattr(torch, dtype)
+    g = torch.Generator().manual_seed(7)
+    src = torch.randn(9 * 1000, generator=g, dtype=torch.float64).to(dt).to("cuda:0")
+    dst = torch.zeros_like(src)
+    _say(f"[gpu] copy probe {dtype}")
+    t2s2.copy_probe(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src.view(torch.int8 if dt != torch.float16 else torch.int16),
+                       dst.view(torch.int8 if dt != torch.float16 else torch.int16))
