@@ -851,13 +851,28 @@ __global__ __launch_bounds__(256) void moments_kernel(AuxParams a, const Store* 
   }
 }
 
+// Sum (or max) over the 64 lanes of a wave by a butterfly of lane exchanges
+// (__shfl_xor); every lane ends with the same result (a + b = b + a), formed
+// in the same order on every run.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, kLanes);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v = fmax(v, __shfl_xor(v, m, kLanes));
+  return v;
+}
+
 // Deterministic two-pass reduction: fixed grid of kDiagBlocks blocks, each
-// thread accumulates a fixed grid-stride subset, blocks reduce through an
-// LDS tree, one final block reduces the partials in block order.
+// thread accumulates a fixed grid-stride subset, each wave reduces its lanes
+// with wave_sum / wave_max, the block adds its four wave results in wave
+// order, and one final block reduces the partials in block order.
 template <typename Store>
 __global__ __launch_bounds__(256) void diag_partial_kernel(AuxParams a, const Store* state,
                                                            double* partials) {
-  __shared__ double red[kDiagSlots][256];
+  __shared__ double red[kDiagSlots][256 / kLanes];
   double acc[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
   const long long n = static_cast<long long>(a.nx) * a.ny;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
@@ -877,22 +892,19 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(AuxParams a, const St
       acc[3] += 1.0;
     }
   }
+  const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
 #pragma unroll
-  for (int k = 0; k < kDiagSlots; ++k) red[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-#pragma unroll
-      for (int k = 0; k < kDiagSlots; ++k) {
-        if (k == 2)
-          red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + w]);
-        else
-          red[k][threadIdx.x] += red[k][threadIdx.x + w];
-      }
-    }
-    __syncthreads();
+  for (int k = 0; k < kDiagSlots; ++k) {
+    const double v = k == 2 ? wave_max(acc[k]) : wave_sum(acc[k]);
+    if (lane == 0) red[k][wave] = v;
   }
-  if (threadIdx.x < kDiagSlots) partials[blockIdx.x * kDiagSlots + threadIdx.x] = red[threadIdx.x][0];
+  __syncthreads();
+  if (threadIdx.x < kDiagSlots) {
+    const int k = threadIdx.x;
+    double v = red[k][0];
+    for (int w = 1; w < 256 / kLanes; ++w) v = k == 2 ? fmax(v, red[k][w]) : v + red[k][w];
+    partials[blockIdx.x * kDiagSlots + k] = v;
+  }
 }
 
 __global__ __launch_bounds__(64) void diag_final_kernel(const double* partials, int nblocks,
@@ -918,7 +930,7 @@ __global__ __launch_bounds__(256) void gre_partial_kernel(AuxParams a, const Sto
                                                           const double* uref,
                                                           const double* vref,
                                                           double* partials) {
-  __shared__ double red[3][256];
+  __shared__ double red[3][256 / kLanes];
   double acc[3] = {0.0, 0.0, 0.0};
   const long long n = static_cast<long long>(a.nx) * a.ny;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
@@ -932,20 +944,23 @@ __global__ __launch_bounds__(256) void gre_partial_kernel(AuxParams a, const Sto
     acc[1] += ur * ur + vr * vr;
     acc[2] += u * u + v * v;
   }
+  const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-    }
-    __syncthreads();
+  for (int k = 0; k < 3; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) red[k][wave] = v;
   }
+  __syncthreads();
   if (threadIdx.x < kDiagSlots) {
     const int k = threadIdx.x;
+    double v[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      v[j] = red[j][0];
+      for (int w = 1; w < 256 / kLanes; ++w) v[j] += red[j][w];
+    }
     partials[blockIdx.x * kDiagSlots + k] =
-        k == 0 ? red[0][0] : (k == 1 ? red[1][0] : (k == 3 ? red[2][0] : 0.0));
+        k == 0 ? v[0] : (k == 1 ? v[1] : (k == 3 ? v[2] : 0.0));
   }
 }
 

@@ -196,6 +196,34 @@ def test_graph_stepping_is_bitwise_plain_stepping(kind, scheme):
     assert a.steps_taken == b.steps_taken == 98
 
 
+def test_cavity257_full_50000_steps():
+    """The whole cavity 257^2 configuration (tanh mesh c = 1.5, Re 1000, CFL
+    0.9, eta 0.1, rest + 1e-6 noise from seed 0, 50000 steps, T = 53.2) in
+    one captured-graph run: its time, and the flow it reaches (bounded by
+    the lid speed, finite, mass kept).  Its first 5000 steps are checked
+    against the oracle above; the paper's steady vortex centre is not
+    reached at T = 53, so no flow value is compared."""
+    case = _cavity257()
+    _say("[gpu] cavity257: 50000 steps")
+    ctx = t2s2.context_for_case(case, stream=torch.cuda.Stream())
+    ctx.init_macro(case.rho0, case.ux0, case.uy0)
+    m0 = ctx.diagnostics()["mass_excess"]
+    ctx.graph_capture(100)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    ctx.graph_step(50000)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d = ctx.diagnostics()
+    _say(f"    {ms / 50:.1f} us/step ({case.nx * case.ny * 50000 / ms / 1e3:.0f} MLUPS), "
+         f"T = {50000 * ctx.dt:.2f}, max|u| {d['max_speed']:.4e}, E {d['kinetic_energy']:.4e}, "
+         f"mass excess {m0:.3e} -> {d['mass_excess']:.3e}")
+    assert ctx.steps_taken == 50000
+    assert d["nonfinite"] == 0 and 0.0 < d["max_speed"] <= 0.1 + 1e-9
+    assert abs(d["mass_excess"] - m0) <= 1e-3
+
+
 def test_cavity257_graph_vs_plain_throughput():
     """MLUPS of the 257^2 cavity (a launch-bound size) with plain launches
     and with a captured 100-step graph; both must agree bitwise."""
@@ -254,15 +282,21 @@ def test_cavity2049_precision_forms_after_20000_steps():
     bounds only catch a broken form."""
     case = _cavity2049()
     ux0, uy0, rho0 = case.ux0, case.uy0, case.rho0
-    vel = {}
+    vel, ms = {}, {}
     for storage in ("f64", "f32", "f16", "bf16"):
         _say(f"[gpu] cavity2049 storage={storage}: 20000 steps")
         ctx = t2s2.context_for_case(case, storage=storage)
         ctx.init_macro(rho0, ux0, uy0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
         ctx.step(20000)
+        e1.record(ctx.stream)
         vel[storage] = _vel(ctx)
+        ms[storage] = e0.elapsed_time(e1)
         diag = ctx.diagnostics(raise_nonfinite=False)
-        _say(f"    max|u| {diag['max_speed']:.4e}  nonfinite {diag['nonfinite']}")
+        _say(f"    {ms[storage] / 20:.1f} us/step ({case.nx * case.ny * 20000 / ms[storage] / 1e3:.0f} "
+             f"MLUPS, {ms['f64'] / ms[storage]:.2f}x FP64)  max|u| {diag['max_speed']:.4e}  "
+             f"nonfinite {diag['nonfinite']}")
         ctx.close()
         del ctx
     bounds = {"f32": 1e-3, "f16": 0.5, "bf16": 1.0}
