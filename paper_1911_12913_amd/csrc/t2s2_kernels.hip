@@ -7,9 +7,9 @@
 //   S = P - h xi . grad_m P            half-step characteristic (eqs 2.33, 2.35)
 //   R = f(t*) from S                   pointwise with new moments (eqs 2.32, 2.52)
 //   f~^{n+1} = Q - dt xi . grad_m R    (eq 2.23)
-// with non-equilibrium extrapolation (eq 3.10) on wall nodes: for R inside
-// the fused kernel (the stencil reads it), for the new state in a small
-// perimeter kernel that follows it.  All populations are carried as
+// with non-equilibrium extrapolation (eq 3.10) on wall nodes, for R (the
+// stencil reads it) and for the new state, both written by the lane of the
+// wall node's nearest interior node.  All populations are carried as
 // deviations g = f~ - w.
 //
 // Work decomposition: a block owns a strip of 64 columns (56 outputs plus a
@@ -111,10 +111,84 @@ __device__ inline Real force_term(int q, const StepParams& p, Real ux, Real uy, 
   return Real(3.0 * w_of(q)) * fu * (Real(1) + E);
 }
 
+// Wall nodes of the new state (eq 3.10),
+//   f~_b = f~_f + f^eq(rho_f, u_b) - f^eq(rho_f, u_f),
+// from the moments of the stored new state at the nearest interior node f
+// (diagonal at the corners), u_f with the force shift of eq 3.3.  Run by a
+// strip's threads after its piece [y0, y1) has been marched and the block
+// has passed a barrier: the sources are the nodes next to a wall among the
+// piece's outputs (columns [x0, x1)), which this block has just stored, so
+// the loads see them (the coherence point is L2; the buffer was not read
+// earlier in the launch).  Each wall node has exactly one source node, and
+// each source node is output by exactly one piece.
+template <typename Store>
+__device__ inline void piece_walls(const StepParams& p, Store* dst, int x0, int x1, int y0,
+                                   int y1, int tid, int nthreads) {
+  using Real = typename Cvt<Store>::R;
+  const int nx = p.nx, ny = p.ny;
+  // Interior output columns and rows of this strip-piece.
+  const int cx0 = p.per_x ? x0 : max(x0, 1), cx1 = p.per_x ? x1 : min(x1, nx - 1);
+  const int ry0 = p.per_y ? y0 : max(y0, 1), ry1 = p.per_y ? y1 : min(y1, ny - 1);
+  if (cx0 >= cx1 || ry0 >= ry1) return;
+  // Sources: (a) the rows next to the bottom and top walls, every column;
+  // (b) the columns next to the left and right walls, the other rows.
+  const bool rb = !p.per_y && ry0 <= 1 && 1 < ry1;
+  const bool rt = !p.per_y && ry0 <= ny - 2 && ny - 2 < ry1;
+  const bool cl = !p.per_x && cx0 <= 1 && 1 < cx1;
+  const bool cr = !p.per_x && cx0 <= nx - 2 && nx - 2 < cx1;
+  const int ncol = cx1 - cx0;
+  const int nrow_a = (rb ? 1 : 0) + (rt ? 1 : 0);
+  const int nrows_b = (ry1 - ry0) - nrow_a;  // rows not already in (a)
+  const int nsrc = nrow_a * ncol + ((cl ? 1 : 0) + (cr ? 1 : 0)) * nrows_b;
+#pragma unroll 1
+  for (int k = tid; k < nsrc; k += nthreads) {
+    int i, j;
+    if (k < nrow_a * ncol) {
+      j = (k < ncol && rb) ? 1 : ny - 2;
+      i = cx0 + k % ncol;
+    } else {
+      const int kb = k - nrow_a * ncol;
+      i = (kb < nrows_b && cl) ? 1 : nx - 2;
+      // The (kb mod nrows_b)-th row of [ry0, ry1) other than rows 1 and
+      // ny - 2 when those are in (a): row 1 is then ry0, row ny - 2 is ry1 - 1.
+      j = ry0 + (rb ? 1 : 0) + kb % nrows_b;
+    }
+    const long long fb = static_cast<long long>(j) * p.pitch + i;
+    Real v[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(dst[q * p.plane + fb]);
+    double s, jx, jy;
+    moment_sums(v, s, jx, jy);
+    const double rho = 1.0 + s;
+    const double ir = recip(rho);
+    const double ux = jx * ir + p.half_dt * p.Fx;
+    const double uy = jy * ir + p.half_dt * p.Fy;
+    const bool wl = !p.per_x && i == 1, wr = !p.per_x && i == nx - 2;
+    const bool wb = !p.per_y && j == 1, wt = !p.per_y && j == ny - 2;
+#pragma unroll 1
+    for (int dy = -1; dy <= 1; ++dy) {
+      if ((dy == -1 && !wb) || (dy == 1 && !wt)) continue;
+#pragma unroll 1
+      for (int dx = -1; dx <= 1; ++dx) {
+        if ((dx == -1 && !wl) || (dx == 1 && !wr)) continue;
+        if (dx == 0 && dy == 0) continue;
+        double ub, vb;
+        wall_velocity(p, i + dx, j + dy, ub, vb);
+        Real sh[kQ];
+        nee_shift(rho, ux, uy, ub, vb, sh);
+        const long long wo = static_cast<long long>(j + dy) * p.pitch + (i + dx);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) dst[q * p.plane + wo] = Cvt<Store>::st(v[q] + sh[q]);
+      }
+    }
+  }
+}
+
 // Resident waves per SIMD the register allocation must allow: the FP64 rings
 // (68 KB per block) admit two blocks per CU; the FP32 rings admit four, which
-// the plain periodic FP32 / FP16 variants reach without spilling (the wall
-// and force variants, and BF16 with its conversions, settle for three).
+// the FP32 / FP16 variants without a force reach without spilling (the force
+// variants, the walled FP16 ones, and BF16 with its conversions, settle for
+// three).
 // T2S2-FDLBM2's wider first ring (106 KB in FP64, 53 KB in FP32) admits one
 // and three blocks per CU.
 // The family's ring (140 KB in FP64, 70 KB in FP32) admits one and two.
@@ -123,7 +197,8 @@ constexpr int kMinWaves =
     sizeof(typename Cvt<Store>::R) == 8
         ? (kScheme == 1 ? 2 : 1)
         : (kScheme == 3 ? 2
-                        : ((kScheme == 2 || kForce || kWalls || std::is_same<Store, Bf16>::value)
+                        : ((kScheme == 2 || kForce || std::is_same<Store, Bf16>::value ||
+                            (kWalls && !std::is_same<Store, float>::value))
                                ? 3
                                : 4));
 
@@ -483,7 +558,10 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
       iteration(it, gA, qA, qB);
       iteration(it + 1, gB, qB, qA);
     }
-    __syncthreads();  // the next piece reuses the rings
+    __syncthreads();  // the next piece reuses the rings; the piece's stores are visible
+    // The adjoint's recompute reads the new state at interior nodes only.
+    if (kWalls && !kSaveS)
+      piece_walls(p, dst, x0, x1, y0, y1, threadIdx.x % kBlockThreads, kBlockThreads);
   }
 }
 
@@ -497,8 +575,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
 // row four above.  Strips are those of step_kernel (56 outputs; the stencil
 // uses 2 of the 4 halo columns each side), marched from 2 rows above the
 // piece instead of 4.  Wall nodes of R take eq 3.10 from their
-// nearest interior node, written by that node's lane; the new state's wall
-// nodes are set by wall_fixup_kernel, as for step_kernel.  Each output takes
+// nearest interior node, written by that node's lane, and so do the new
+// state's wall nodes, as in step_kernel.  Each output takes
 // the same expressions in the same order as step_kernel at A = 0 (where
 // S = P + 0 L(P) and R = 1 S + 0 E reproduce P).
 //
@@ -707,59 +785,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, 0), (kMinWaves<Stor
       iteration(it, gA, qA, qB);
       iteration(it + 1, gB, qB, qA);
     }
-    __syncthreads();  // the next piece reuses the ring
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Wall nodes of the new state (eq 3.10): f~_b = f~_f + f^eq(rho_f, u_b) -
-// f^eq(rho_f, u_f) from the nearest interior node f (diagonal at corners;
-// x-walls own the corners).  Runs after the fused step on walled domains.
-// ---------------------------------------------------------------------------
-template <typename Store>
-__global__ __launch_bounds__(256) void wall_fixup_kernel(StepParams p) {
-  using Real = typename Cvt<Store>::R;
-  Store* __restrict__ st = static_cast<Store*>(p.dst);
-  const int nx = p.nx, ny = p.ny;
-  // Perimeter enumeration: bottom row, top row, left column, right column;
-  // the columns skip the rows that the row lists already cover.
-  const int nrow = p.per_y ? 0 : nx;
-  const int ncol = p.per_x ? 0 : (p.per_y ? ny : ny - 2);
-  const int total = 2 * nrow + 2 * ncol;
-  for (int k = blockIdx.x * 256 + threadIdx.x; k < total; k += 256 * gridDim.x) {
-    int i, j;
-    if (k < nrow) {
-      i = k;
-      j = 0;
-    } else if (k < 2 * nrow) {
-      i = k - nrow;
-      j = ny - 1;
-    } else if (k < 2 * nrow + ncol) {
-      i = 0;
-      j = (k - 2 * nrow) + (p.per_y ? 0 : 1);
-    } else {
-      i = nx - 1;
-      j = (k - 2 * nrow - ncol) + (p.per_y ? 0 : 1);
-    }
-    const int fi = p.per_x ? i : clampi(i, 1, nx - 2);
-    const int fj = p.per_y ? j : clampi(j, 1, ny - 2);
-    const long long fb = static_cast<long long>(fj) * p.pitch + fi;
-    Real v[kQ];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(st[q * p.plane + fb]);
-    double s, jx, jy;
-    moment_sums(v, s, jx, jy);
-    const double rho = 1.0 + s;
-    const double ir = recip(rho);
-    const double ux = jx * ir + p.half_dt * p.Fx;
-    const double uy = jy * ir + p.half_dt * p.Fy;
-    double ub, vb;
-    wall_velocity(p, i, j, ub, vb);
-    Real sh[kQ];
-    nee_shift(rho, ux, uy, ub, vb, sh);
-    const long long wb = static_cast<long long>(j) * p.pitch + i;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) st[q * p.plane + wb] = Cvt<Store>::st(v[q] + sh[q]);
+    __syncthreads();  // the next piece reuses the ring; the piece's stores are visible
+    if (kWalls) piece_walls(p, dst, x0, x1, y0, y1, threadIdx.x % kBlockThreads, kBlockThreads);
   }
 }
 
@@ -1006,10 +1033,6 @@ hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
     launch_fused<Store, 3>(p, g, b, s, walls);
   else
     launch_fused<Store, 1>(p, g, b, s, walls);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !walls) return e;
-  const int perim = 2 * (p.nx + p.ny);
-  hipLaunchKernelGGL(wall_fixup_kernel<Store>, dim3((perim + 255) / 256), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 
