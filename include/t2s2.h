@@ -97,7 +97,9 @@ typedef struct t2s2_ctx t2s2_ctx;
  * strictly increasing; on a walled axis the first and last nodes are walls;
  * on a periodic axis x[nx-1] - x[0] < period).  Validates nx, ny >= 5,
  * 0 < cfl <= 1 (unless dt > 0), nu > 0, 0 <= eta <= 1, 0 <= A <= 1, and
- * computes dt and the stencil coefficients on the host.  One population
+ * computes dt and the stencil coefficients on the host.  T2S2_FDLBM1 with
+ * A = 0 (T1S2) runs a single-stencil step kernel (the half step is then the
+ * identity); the values are those of the general step.  One population
  * plane (ny * pitch elements of the storage type) must be under 4 GiB
  * (T2S2_ERR_UNSUPPORTED otherwise; FP64 up to about 23000 x 23000 nodes).
  * No device call. */
@@ -113,7 +115,11 @@ size_t t2s2_state_bytes(const t2s2_ctx* ctx);
 size_t t2s2_workspace_bytes(const t2s2_ctx* ctx);
 
 /* Attach two state buffers (ping-pong), the workspace and a hipStream_t
- * (NULL = default stream).  Uploads the weight tables; synchronises. */
+ * (NULL = default stream).  Uploads the weight tables; synchronises.  Plans
+ * the step's launch from the device's CU count and the step kernel's
+ * occupancy; if the environment variable T2S2_BLOCKS is set, its value
+ * (rounded down to a multiple of 8, at least 8) replaces the block count, a
+ * hook for checking that results do not depend on the tiling. */
 int t2s2_bind(t2s2_ctx* ctx, void* state_a, void* state_b, void* workspace, void* stream);
 
 /* f~ = f^eq(rho, u) (Sec. 3), minus the non-equilibrium part of eq 3.5
