@@ -228,3 +228,45 @@ def test_adjoint_step_time_513(storage):
         us = e0.elapsed_time(e1) / 50 * 1e3
         print(f"    513^2 {storage} {label}: {us:.1f} us "
               f"({case.nx * case.ny / us:.0f} MLUPS)", flush=True)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_step_time_4096(storage):
+    """Time of one adjoint step on the periodic 4096^2 Taylor-Green grid,
+    where the state and the adjoint buffers are far larger than the caches:
+    its algorithmic bytes per node (the recompute reads the state and writes
+    the next state and S; the reverse march reads the state, lambda^{n+1}
+    and S and writes lambda^n) over the step time, against the HBM peak;
+    reported."""
+    case = W.tgv_case(4096, 4096, u0=0.01, nu=1e-4, cfl=0.9, eta=0.01)
+    print(f"[gpu] adjoint step 4096^2 {storage}", flush=True)
+    ctx = t2s2.context_for_case(case, storage=storage)
+    ctx.enable_adjoint()
+    ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
+    state = ctx.save_state()
+    lam_a, lam_b = ctx.adjoint_buffer(), ctx.adjoint_buffer()
+    gu = _dev(W.random_state((case.ny, case.nx), 1.0, 3))
+    ctx.adjoint_seed_velocity(state, gu, gu, lam_a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sb = 8 if storage == "f64" else 4  # storage and arithmetic bytes per value
+    per_node = {"forward step": 18 * sb, "adjoint step": 9 * (3 * sb) + 9 * (4 * sb)}
+    for label, fn in (("forward step", lambda: ctx.step(1)),
+                      ("adjoint step", lambda: ctx.adjoint_step(state, lam_a, lam_b))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(ctx.stream)
+        for _ in range(20):
+            fn()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 20 * 1e3
+        gbs = per_node[label] * case.nx * case.ny / (us * 1e-6) / 1e9
+        print(f"    4096^2 {storage} {label}: {us:.1f} us ({case.nx * case.ny / us:.0f} MLUPS, "
+              f"{per_node[label]} B/node, {gbs:.0f} GB/s = {gbs / 8000:.3f} of 8 TB/s)", flush=True)
+    lam = ctx.adjoint_read(lam_b)
+    assert bool(torch.isfinite(lam).all()) and float(lam.abs().max()) > 0
+    del lam
+    ctx.close()
+    del ctx, state, lam_a, lam_b
+    torch.cuda.empty_cache()
