@@ -575,8 +575,9 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
 // row four above.  Strips are those of step_kernel (56 outputs; the stencil
 // uses 2 of the 4 halo columns each side), marched from 2 rows above the
 // piece instead of 4.  Wall nodes of R take eq 3.10 from their
-// nearest interior node, written by that node's lane, and so do the new
-// state's wall nodes, as in step_kernel.  Each output takes
+// nearest interior node, written by that node's lane; the new state's wall
+// nodes are set after each piece (piece_walls), as in step_kernel.  Each
+// output takes
 // the same expressions in the same order as step_kernel at A = 0 (where
 // S = P + 0 L(P) and R = 1 S + 0 E reproduce P).
 //

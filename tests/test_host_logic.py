@@ -154,3 +154,15 @@ def test_stencil_weights_argument_checks():
         assert lib.t2s2_stencil_weights(h, None, None) == t2s2.OK
     finally:
         lib.t2s2_destroy(h)
+
+
+def test_bench_refuses_more_than_one_gpu(capsys):
+    """bench.py runs on one GPU: --gpus above 1 exits with status 2 and a
+    message, before any device call."""
+    import json
+
+    import bench
+
+    assert bench.main(["--gpus", "2"]) == 2
+    rec = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert rec["n_gpus"] == 2 and "one GPU" in rec["error"]
