@@ -189,25 +189,37 @@ __device__ inline void piece_walls(const StepParams& p, Store* dst, int x0, int 
 // the FP32 / FP16 variants without a force reach without spilling (the force
 // variants, the walled FP16 ones, and BF16 with its conversions, settle for
 // three).
-// T2S2-FDLBM2's wider first ring (106 KB in FP64, 53 KB in FP32) admits one
-// and three blocks per CU.
+// T2S2-FDLBM2's first ring (106 KB in FP64, 53 KB in FP32) admits one and
+// three blocks per CU; in FP64 on periodic meshes it holds Q alone, as
+// FDLBM1's holds P, and admits two blocks.
 // The family's ring (140 KB in FP64, 70 KB in FP32) admits one and two.
 template <typename Store, bool kForce, bool kWalls, int kScheme>
 constexpr int kMinWaves =
     sizeof(typename Cvt<Store>::R) == 8
-        ? (kScheme == 1 ? 2 : 1)
+        ? ((kScheme == 1 || (kScheme == 2 && !kWalls)) ? 2 : 1)
         : (kScheme == 3 ? 2
                         : ((kScheme == 2 || kForce || std::is_same<Store, Bf16>::value ||
                             (kWalls && !std::is_same<Store, float>::value))
                                ? 3
                                : 4));
 
+// T2S2-FDLBM2 in FP64 on a periodic mesh forms each row's f^n again, in the
+// wave that needs it, from the row reloaded from cache, instead of keeping
+// it in the first LDS ring: the ring then admits two blocks per CU (FP64
+// 792 -> 653 us per step at 4096^2).  The FP32-arithmetic forms, bound by
+// their vector instructions, keep the ring (the recompute made FP32 15%
+// slower).
+template <typename Store, bool kWalls, int kScheme>
+constexpr bool kReloadFnOf =
+    kScheme == 2 && !kWalls && sizeof(typename Cvt<Store>::R) == 8;
+
 // Planes of the first LDS ring: P for T2S2-FDLBM1 (and T1S2); for
 // T2S2-FDLBM2, Q = f~^+ (the field the prediction advects) and, for the
-// eight moving directions, the physical f^n; for the family, P, Q and the
-// eight moving directions of f^n.
-template <int kScheme>
-constexpr int kPPlanes = kScheme == 1 ? kQ : (kScheme == 2 ? 2 * kQ - 1 : 3 * kQ - 1);
+// eight moving directions, the physical f^n (not with kReloadFnOf); for the
+// family, P, Q and the eight moving directions of f^n.
+template <int kScheme, bool kReload>
+constexpr int kPPlanes =
+    kScheme == 1 ? kQ : (kScheme == 2 ? (kReload ? kQ : 2 * kQ - 1) : 3 * kQ - 1);
 
 // The fused step, templated on the storage type, the presence of a body
 // force, of walls, on the scheme, and on kSaveS (the discrete adjoint's
@@ -224,7 +236,9 @@ template <typename Store, bool kForce, bool kWalls, int kScheme, bool kSaveS = f
 __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWaves<Store, kForce, kWalls, kScheme>)) void step_kernel(
     StepParams p) {
   using Real = typename Cvt<Store>::R;
-  constexpr int kNP = kPPlanes<kScheme>;
+  // T2S2-FDLBM2, FP64, periodic: f^n of the phase-2 row from a reload.
+  constexpr bool kReloadFn = kReloadFnOf<Store, kWalls, kScheme>;
+  constexpr int kNP = kPPlanes<kScheme, kReloadFn>;
   constexpr int kSB = strips_per_block(kStorageOf<Store>, kScheme);
   constexpr int kThreads = step_threads(kStorageOf<Store>, kScheme);
   constexpr int kSizeP = kRing * kNP * kLanes, kSizeR = kRing * (kQ - 1) * kLanes;
@@ -339,6 +353,11 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
 
       // ---- phase 1: P (to LDS) and Q (registers) of row p0 + t; for
       // T2S2-FDLBM2 Q and f^n to LDS (P's coefficients then give f^n).
+      // With kReloadFn the row of phase 2 is loaded again here (a cache hit:
+      // the block loaded it at most one iteration ago), so that its f^n can
+      // be formed there.
+      Store gn[kQ];
+      if constexpr (kReloadFn) load_row(p0 - 2 + t, gn);
       {
         const int pr = p0 + t;
         Real g[kQ];
@@ -374,7 +393,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
             Qq += static_cast<Real>(p.cQF) * Fq;
           }
           slotP[q * kLanes + lane] = kScheme == 2 ? Qq : Pq;
-          if (kScheme == 2 && q > 0) slotP[(kQ + q - 1) * kLanes + lane] = Pq;
+          if (kScheme == 2 && !kReloadFn && q > 0) slotP[(kQ + q - 1) * kLanes + lane] = Pq;
           if (kScheme == 3) {
             slotP[(kQ + q) * kLanes + lane] = Qq;
             if (q > 0) {
@@ -463,12 +482,41 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
             Real S2[kQ];
             predict(kQ, Real(1), k.cU, k.kU, p.cUF, p.half_dt, S2, R2, rho2, ux2, uy2);
           }
+          // f^n of this node from the reloaded row (kReloadFn), with the
+          // expressions of phase 1.
+          Real fn[kQ];
+#pragma unroll
+          for (int q = 0; q < kQ; ++q) fn[q] = Real(0);
+          if constexpr (kReloadFn) {
+            Real g2[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) g2[q] = Cvt<Store>::ld(gn[q]);
+            double s2, jx2, jy2;
+            moment_sums(g2, s2, jx2, jy2);
+            Real rho0, ux0, uy0;
+            velocity(s2, jx2, jy2, rho0, ux0, uy0);
+            if (kForce) {
+              ux0 += static_cast<Real>(p.half_dt * p.Fx);
+              uy0 += static_cast<Real>(p.half_dt * p.Fy);
+            }
+            const Real d0 = static_cast<Real>(s2);
+            Real X0[kQ];
+            eq_brackets(ux0, uy0, X0);
+#pragma unroll
+            for (int q = 1; q < kQ; ++q) {
+              const Real E = d0 + rho0 * X0[q];
+              Real Pq = k.cPg * g2[q] + k.kP[wclass(q)] * E;
+              if (kForce) Pq += static_cast<Real>(p.cPF) * force_term(q, p, ux0, uy0, E);
+              fn[q] = Pq;
+            }
+          }
           // T, the field whose gradient the full step takes: R (scheme 1),
           // f^n + R (scheme 2, halved in phase 3), b0 f^n + b1 R + b2 R2
-          // (scheme 3); f^n of (row, ln) from the ring.
+          // (scheme 3); f^n of (row, ln) from the ring (from fn with
+          // kReloadFn, where (row, ln) is always this node).
           auto t_of = [&](int q, int row, int ln, Real r1, Real r2) {
             const Real* slot = ringP + (row & (kRing - 1)) * kNP * kLanes + ln;
-            if (kScheme == 2) return r1 + slot[(kQ + q - 1) * kLanes];
+            if (kScheme == 2) return r1 + (kReloadFn ? fn[q] : slot[(kQ + q - 1) * kLanes]);
             if (kScheme == 3)
               return k.b[0] * slot[(2 * kQ + q - 1) * kLanes] + k.b[1] * r1 + k.b[2] * r2;
             return r1;

@@ -80,6 +80,29 @@ def test_tgv4096_bench_configuration_matches_oracle(monkeypatch):
         torch.cuda.empty_cache()
 
 
+def test_tgv4096_t1s2_bench_configuration_matches_oracle(monkeypatch):
+    """bench.py's T1S2 line (A = 0, the single-stencil kernel): TGV 4096^2,
+    nu 1e-4, CFL 0.25, eta 0.01, eq 3.5 initial state, two steps in the
+    default launch configuration; relative L2 <= 1e-12 on the state and on
+    (u, v) against the oracle's A = 0 march over the whole grid."""
+    monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+    case = W.tgv_case(4096, 4096, u0=0.01, nu=1e-4, cfl=0.25, eta=0.01, A=0.0)
+    _say("[gpu] tgv4096 T1S2: oracle init + 2 steps on the host")
+    ref = oracle.run(case, oracle.init(case), 2, threads=_host_threads(), A=0.0)
+    _, ur, vr = oracle.moments(case, ref)
+    ctx = t2s2.context_for_case(case, storage="f64", A=0.0)
+    ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
+    ctx.step(2)
+    ev = _rel(_vel(ctx), np.stack([ur, vr]))
+    g = ctx.read_distributions().cpu().numpy()
+    eg = _rel(g, ref)
+    _say(f"    T1S2: (u,v) rel L2 {ev:.3e}  state rel L2 {eg:.3e}")
+    assert eg <= 1e-12 and ev <= 1e-12
+    ctx.close()
+    del ctx, g
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_tgv4096_scheme_throughput(storage, monkeypatch):
     """Step time of the three schemes on the 4096^2 Taylor-Green workload

@@ -289,6 +289,24 @@ def test_fdlbm2_periodic_matches_oracle():
     _compare(case, g, d, u, v, ref)
 
 
+def test_fdlbm2_periodic_forced_and_tiled_matches_oracle(monkeypatch):
+    """T2S2-FDLBM2 on a periodic mesh forms f^n of each node again from its
+    row (no f^n ring): the periodic 150x70 Taylor-Green with a uniform body
+    force, 100 steps, against the oracle, bitwise the same state for three
+    block counts."""
+    case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.5, eta=0.05)
+    case.force = np.array([2e-4, -1e-4])
+    phi0 = oracle.init(case) + W.random_state((9, 70, 150), 1e-5, 8)
+    ref = oracle.run(case, phi0, 100, scheme=2)
+    outs = []
+    for blocks in ("8", "40", "96"):
+        monkeypatch.setenv("T2S2_BLOCKS", blocks)
+        _, g, d, u, v = _gpu_run(case, phi0, 100, scheme=2)
+        _compare(case, g, d, u, v, ref)
+        outs.append(g)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
 @pytest.mark.parametrize("blocks", ["8", "16", "40"])
 def test_fdlbm2_walled_cavity_matches_oracle(blocks, monkeypatch):
     """T2S2-FDLBM2 on the ragged 130x65 cavity (walls on all sides, moving
