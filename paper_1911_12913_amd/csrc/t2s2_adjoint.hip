@@ -250,12 +250,22 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
   double dw = 0.0;
   for (int i = threadIdx.x; i < kRing * kQ * kLanes; i += 256) ring[i] = Real(0);
 
+  // y weight of tap k, sign class sc, of the stencil at source row yi
+  // (wave-uniform: read through the constant address space so it becomes a
+  // scalar load, which the vector-memory counter does not wait for).
+  using CReal = const __attribute__((address_space(4))) Real*;
+  auto ywt = [&](int yi, int sc, int k) {
+    const int idx = __builtin_amdgcn_readfirstlane(yi * kWeightsPerNode + sc * kTaps + k);
+    return ((CReal)(WY))[idx];
+  };
+
   // lamR of population q at (c, y) from the rows around (y taps only, over
-  // interior source rows): the wall rows' lamR, and the y part of the
-  // interior rows'.  y is a row inside the grid; the caller zeroes wall
-  // columns.  In FP32 every tap loads (from row y when its source row is
-  // not interior, with weight 0), so the four loads issue together; FP64
-  // skips those loads, which keeps its registers within two waves per SIMD.
+  // interior source rows), for the wall rows (the interior rows' y taps are
+  // loaded with the rest of phase A's loads below).  y is a row inside the
+  // grid; the caller zeroes wall columns.  In FP32 every tap loads (from row
+  // y when its source row is not interior, with weight 0), so the four loads
+  // issue together; FP64 skips those loads, which keeps its registers within
+  // two waves per SIMD.
   auto lamR_y = [&](int q, int c, int y) {
     Real acc = Real(0);
     if (ey_of(q) == 0) return acc;
@@ -314,6 +324,35 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
           const bool row_int = a.per_y || (r >= 1 && r <= ny - 2);
           const bool nin = col_int && row_int;
           const long long roff = static_cast<long long>(r) * a.pitch + c;
+          // Every load of the phase, issued together before any of it is
+          // used (a load followed at once by its use waits out the whole
+          // memory latency, once per population): mu at (c, r) for the
+          // x-moving populations, the y taps of L^T mu (from row r, with
+          // weight 0, where the source row is not interior) and S at (c, r).
+          // 20% faster at 513^2, 30% at 4096^2, the same values.
+          Real mvx[kQ], myt[kQ][kTaps], wys[2][kTaps], sv[kQ];
+          int ysrc[2][kTaps];
+#pragma unroll
+          for (int sc = 0; sc < 2; ++sc) {
+#pragma unroll
+            for (int k = 0; k < kTaps; ++k) {
+              const int yi = along(r, -tap_offset(sc, k), ny, a.per_y);
+              const bool rok = yi >= 0 && (a.per_y || (yi >= 1 && yi <= ny - 2));
+              ysrc[sc][k] = rok ? yi : r;
+              wys[sc][k] = rok ? ywt(yi, sc, k) : Real(0);
+            }
+          }
+#pragma unroll
+          for (int q = 1; q < kQ; ++q) {
+            mvx[q] = ex_of(q) != 0 ? mu[q * plane + roff] : Real(0);
+            if (ey_of(q) != 0) {
+              const int s = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+              for (int k = 0; k < kTaps; ++k)
+                myt[q][k] = mu[q * plane + static_cast<long long>(ysrc[s][k]) * a.pitch + c];
+            }
+          }
+          load9(S, plane, roff, sv);
           Real lr[kQ];
           lr[0] = Real(0);
 #pragma unroll
@@ -321,7 +360,7 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
             // x part: sources (c - o_k, r), o_k the tap offset
             Real acc = Real(0);
             if (ex_of(q) != 0) {
-              const Real mv = mu[q * plane + roff];
+              const Real mv = mvx[q];
               const Real m = nin ? mv : Real(0);
               if (ex_of(q) > 0) {  // o = -2, -1, 0, +1
                 acc = from_above(from_above(wx[0] * m)) + from_above(wx[1] * m) + wx[2] * m +
@@ -331,7 +370,12 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
                       from_below(from_below(wx[7] * m));
               }
             }
-            const Real ly = row_int ? lamR_y(q, c, r) : Real(0);
+            Real lyv = Real(0);
+            if (ey_of(q) != 0) {
+#pragma unroll
+              for (int k = 0; k < kTaps; ++k) lyv += wys[ey_of(q) > 0 ? 0 : 1][k] * myt[q][k];
+            }
+            const Real ly = row_int ? lyv : Real(0);
             lr[q] = acc + (col_int ? ly : Real(0));
           }
           // lamR of the x-wall neighbour (its own lane computed it above)
@@ -345,8 +389,6 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
             }
           }
           if (nin) {
-            Real sv[kQ];
-            load9(S, plane, roff, sv);
             double rho, ux, uy;
             node_rho_u(sv, rho, ux, uy);
             auto add_wall = [&](int bx, int by, const Real lb[kQ]) {
@@ -394,7 +436,25 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
         const int o = p0 - 2 + t;
         if (o >= y0 && o < y1) {  // uniform per wave
           const bool nin = col_int && (a.per_y || (o >= 1 && o <= ny - 2));
+          // This row's state and mu, loaded before the ring taps so their
+          // latency overlaps them.
+          const long long ooff = static_cast<long long>(o) * a.pitch + c;
+          Real v[kQ], lq[kQ];
+#pragma unroll
+          for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * plane + ooff]);
+          load9(mu, plane, ooff, lq);
           const Real* cen = ring + (o & (kRing - 1)) * kQ * kLanes + lane;
+          // y weights of the taps (zero where the source row is outside a
+          // walled axis; the ring holds zero off the interior).
+          Real wyo[2][kTaps];
+#pragma unroll
+          for (int sc = 0; sc < 2; ++sc) {
+#pragma unroll
+            for (int k = 0; k < kTaps; ++k) {
+              const int yi = along(o, -tap_offset(sc, k), ny, a.per_y);
+              wyo[sc][k] = yi >= 0 ? ywt(yi, sc, k) : Real(0);
+            }
+          }
           Real lp[kQ];
 #pragma unroll
           for (int q = 0; q < kQ; ++q) {
@@ -411,19 +471,11 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
 #pragma unroll
               for (int k = 0; k < kTaps; ++k) {
                 const int yu = o - tap_offset(s, k);  // unwrapped source row
-                const int yi = along(o, -tap_offset(s, k), ny, a.per_y);
-                if (yi >= 0)
-                  acc += WY[yi * kWeightsPerNode + s * kTaps + k] *
-                         ring[(yu & (kRing - 1)) * kQ * kLanes + q * kLanes + lane];
+                acc += wyo[s][k] * ring[(yu & (kRing - 1)) * kQ * kLanes + q * kLanes + lane];
               }
             }
             lp[q] = (nin ? l : Real(0)) + (q == 0 ? Real(0) : A * acc);
           }
-          const long long ooff = static_cast<long long>(o) * a.pitch + c;
-          Real v[kQ], lq[kQ];
-#pragma unroll
-          for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * plane + ooff]);
-          load9(mu, plane, ooff, lq);
           double rho, ux, uy;
           node_rho_u(v, rho, ux, uy);
           Real feq[kQ], mix[kQ];
