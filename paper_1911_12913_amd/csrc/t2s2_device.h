@@ -37,8 +37,7 @@ struct Cvt<float> {
   __device__ static float st(float v) { return v; }
 };
 // BF16 as raw bits: widening is a 16-bit shift; narrowing rounds to nearest
-// even by adding 0x7fff plus the lowest kept bit before truncating (NaN kept
-// quiet).
+// even, with gfx950's conversion instruction (v_cvt_pk_bf16_f32).
 struct Bf16 {
   unsigned short bits;
 };
@@ -47,9 +46,7 @@ struct Cvt<Bf16> {
   using R = float;
   __device__ static float ld(Bf16 v) { return __uint_as_float(static_cast<unsigned>(v.bits) << 16); }
   __device__ static Bf16 st(float v) {
-    const unsigned u = __float_as_uint(v);
-    if (v != v) return Bf16{static_cast<unsigned short>((u >> 16) | 0x40u)};
-    return Bf16{static_cast<unsigned short>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16)};
+    return Bf16{__builtin_bit_cast(unsigned short, static_cast<__bf16>(v))};
   }
 };
 template <>
