@@ -441,7 +441,17 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   if (e != hipSuccess) return hip_fail(e, "bind: device query");
   c->grid = plan_blocks(c->sp, c->cfg.storage, cus);
   c->grid_gen = c->sp.single ? plan_blocks(c->sp_gen, c->cfg.storage, cus) : c->grid;
-  if (!c->sp.single) c->sp_gen = c->sp;
+  // Small meshes take the tile kernel (scheme 1, A > 0), when a march would
+  // leave each block fewer than kTileMaxMarchRows unit-rows; not when the
+  // block count is forced (T2S2_BLOCKS), which selects the march.
+  c->sp.tile = 0;
+  if (c->sp.scheme == 1 && !c->sp.single && !std::getenv("T2S2_BLOCKS") &&
+      static_cast<long long>(c->sp.nunits) * c->ny < static_cast<long long>(kTileMaxMarchRows) * c->grid)
+    c->sp.tile = 1;
+  if (!c->sp.single) {
+    c->sp_gen = c->sp;
+    c->sp_gen.tile = 0;
+  }
   if (c->grid < 1 || c->grid_gen < 1) return fail(T2S2_ERR_HIP, "bind: step kernel cannot be resident");
   c->bound = true;
   c->cur = 0;

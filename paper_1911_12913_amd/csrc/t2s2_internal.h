@@ -24,6 +24,10 @@ constexpr int kStripOut = kLanes - 2 * kHalo;
 // barrier per iteration suffices).
 constexpr int kHalo1 = 2;
 constexpr int kRing1 = 16;
+// The tile kernel (small meshes) takes 8 output rows per block; it replaces
+// the march when a march block would hold fewer unit-rows than this (the
+// crossover measured on cavities from 65^2 to 2049^2, all storages).
+constexpr int kTileMaxMarchRows = 24;
 // Rows advanced per iteration of the y-march = waves per block.
 constexpr int kRowsPerIter = 4;
 constexpr int kBlockThreads = kLanes * kRowsPerIter;
@@ -67,6 +71,8 @@ struct StepParams {
   int scheme;   // 1: T2S2-FDLBM1 family (eq 2.23); 2: T2S2-FDLBM2 (eq 5.23);
                 // 3: the eq 2.13 family with gradient weights b
   int single;   // scheme 1 at A = 0 (T1S2): the single-stencil kernel
+  int tile;     // small mesh, scheme 1 with A > 0: the tile kernel, one block
+                // per strip and kTileRows rows (grid nstrips * row tiles)
   void* save_s; // adjoint recompute only: S in the arithmetic type, else NULL
   const double* wx;   // [nx][2][4] dt-scaled x weights (FP64)
   const double* wy;   // [ny][2][4]

@@ -614,6 +614,231 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
 }
 
 // ---------------------------------------------------------------------------
+// Tile step for small meshes (T2S2-FDLBM1 family).  A block of eight waves
+// takes one strip (56 output columns) and kTileRows output rows as a whole
+// tile instead of marching down a range of rows: it loads the tile's rows
+// y0-4 .. y0+kTileRows+3 at once, forms P of all of them (LDS) and Q of its
+// output rows (registers), then S and R of rows y0-2 .. y0+kTileRows+1
+// (LDS), then the new state: three phases and two barriers, where a march
+// over a few rows runs four pipelined iterations of three phases each.  Each
+// node takes the expressions of step_kernel.  Wave w forms P of tile rows w
+// and w+8 (rows counted from y0-4) and keeps Q of the one that is an output
+// row (w+8 for w < 4, w otherwise), which it outputs in phase 3.
+// ---------------------------------------------------------------------------
+constexpr int kTileRows = 8;
+constexpr int kTileWaves = 8;
+constexpr int kTileIn = kTileRows + 2 * kHalo;   // rows of P
+constexpr int kTileMid = kTileRows + kHalo;      // rows of R
+
+template <typename Store, bool kForce, bool kWalls>
+__global__ __launch_bounds__(kTileWaves * kLanes) void tile_step_kernel(StepParams p) {
+  using Real = typename Cvt<Store>::R;
+  __shared__ Real tP[kTileIn * kQ * kLanes];           // [row][q][lane]
+  __shared__ Real tR[kTileMid * (kQ - 1) * kLanes];    // [row][q-1][lane]
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+  const int nx = p.nx, ny = p.ny;
+  const Store* __restrict__ src = static_cast<const Store*>(p.src);
+  Store* __restrict__ dst = static_cast<Store*>(p.dst);
+  const long long plane = p.plane;
+  const int pitch = static_cast<int>(p.pitch);
+  const int ntiles = (ny + kTileRows - 1) / kTileRows;
+  const int strip = blockIdx.x / ntiles;
+  const int y0 = (blockIdx.x % ntiles) * kTileRows;
+  const int y1 = min(y0 + kTileRows, ny);
+  if (strip >= p.nstrips) return;  // whole block, before any barrier
+
+  for (int i = threadIdx.x; i < kTileMid * (kQ - 1) * kLanes; i += kTileWaves * kLanes)
+    tR[i] = Real(0);
+
+  const int x0 = strip * kStripOut;
+  const int x1 = min(x0 + kStripOut, nx);
+  const int c = x0 - kHalo + lane;
+  const int cm = p.per_x ? wrap(c, nx) : clampi(c, 0, nx - 1);
+  Real wxr[kWeightsPerNode];
+  {
+    const Real* wx = weights_x<Real>(p);
+#pragma unroll
+    for (int k = 0; k < kWeightsPerNode; ++k) wxr[k] = wx[cm * kWeightsPerNode + k];
+  }
+  const bool col_interior = p.per_x || (c >= 1 && c <= nx - 2);
+  const bool lane_r = lane >= 2 && lane < kLanes - 2;
+  const bool lane_o = lane >= kHalo && lane < kLanes - kHalo && c < x1;
+  const bool src_xl = !p.per_x && c == 1;
+  const bool src_xr = !p.per_x && c == nx - 2;
+  const auto& k = coef<Real>(p);
+
+  // ---- phase 1: P of tile rows w and w + 8, Q of the wave's output row.
+  const int jout = w < kHalo ? w + kTileWaves : w;
+  Real qout[kQ];
+  {
+    Store gr[2][kQ];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int pr = y0 - kHalo + w + kTileWaves * h;
+      const int prm = p.per_y ? wrap_near(pr, ny) : clampi(pr, 0, ny - 1);
+      const unsigned boff =
+          (static_cast<unsigned>(prm) * static_cast<unsigned>(pitch) + static_cast<unsigned>(cm)) *
+          static_cast<unsigned>(sizeof(Store));
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) gr[h][q] = *at_byte(src + q * plane, boff);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = w + kTileWaves * h;
+      Real g[kQ];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) g[q] = Cvt<Store>::ld(gr[h][q]);
+      double s, jx, jy;
+      moment_sums(g, s, jx, jy);
+      Real rho, ux, uy;
+      velocity(s, jx, jy, rho, ux, uy);
+      if (kForce) {
+        ux += static_cast<Real>(p.half_dt * p.Fx);
+        uy += static_cast<Real>(p.half_dt * p.Fy);
+      }
+      const Real d = static_cast<Real>(s);
+      Real X[kQ];
+      eq_brackets(ux, uy, X);
+      Real* row = tP + j * kQ * kLanes;
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const Real E = d + rho * X[q];
+        Real Pq = k.cPg * g[q] + k.kP[wclass(q)] * E;
+        Real Qq = k.cQg * g[q] + k.kQ[wclass(q)] * E;
+        if (kForce) {
+          const Real Fq = force_term(q, p, ux, uy, E);
+          Pq += static_cast<Real>(p.cPF) * Fq;
+          Qq += static_cast<Real>(p.cQF) * Fq;
+        }
+        row[q * kLanes + lane] = Pq;
+        if (j == jout) qout[q] = Qq;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: S and R of rows y0 - 2 + m, m = w and w + 8 (m < 12).
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int m = w + kTileWaves * h;
+    if (m >= kTileMid) break;  // uniform per wave
+    const int r = y0 - 2 + m;
+    if (!(p.per_y || (r >= 1 && r <= ny - 2))) continue;
+    const int rm = p.per_y ? wrap_near(r, ny) : r;
+    Real wyr[kWeightsPerNode];
+    row_weights(weights_y<Real>(p), rm, wyr);
+    const Real* rb[5];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) rb[o] = tP + (m + o) * kQ * kLanes + lane;
+    Real S[kQ], R[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int pq = q * kLanes;
+      const Real centre = rb[2][pq];
+      Real acc = Real(0);
+      if (ex_of(q) > 0) acc = x_taps<0>(wxr, centre, acc);
+      if (ex_of(q) < 0) acc = x_taps<1>(wxr, centre, acc);
+      if (ey_of(q) != 0) {
+        const int sy = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+        for (int k2 = 0; k2 < kTaps; ++k2) acc += wyr[sy * kTaps + k2] * rb[k2 + sy][pq];
+      }
+      S[q] = q == 0 ? centre : centre + k.A * acc;
+    }
+    double s, jx, jy;
+    moment_sums(S, s, jx, jy);
+    Real rho, ux, uy;
+    velocity(s, jx, jy, rho, ux, uy);
+    if (kForce) {
+      ux += static_cast<Real>(p.half_h * p.Fx);
+      uy += static_cast<Real>(p.half_h * p.Fy);
+    }
+    const Real d = static_cast<Real>(s);
+    Real X[kQ];
+    eq_brackets(ux, uy, X);
+    R[0] = Real(0);
+#pragma unroll
+    for (int q = 1; q < kQ; ++q) {
+      const Real E = d + rho * X[q];
+      Real Rq = k.cRs * S[q] + k.kR[wclass(q)] * E;
+      if (kForce) Rq += static_cast<Real>(p.cRF) * force_term(q, p, ux, uy, E);
+      R[q] = Rq;
+    }
+    if (lane_r && col_interior) {
+      Real* slot = tR + m * (kQ - 1) * kLanes;
+#pragma unroll
+      for (int q = 1; q < kQ; ++q) slot[(q - 1) * kLanes + lane] = R[q];
+      // Wall nodes whose nearest interior node is this one (eq 3.10 on
+      // f(t*); corners take the diagonal neighbour); a wall row past the
+      // tile's last R row is read by none of its outputs.
+      const bool src_yb = !p.per_y && r == 1;
+      const bool src_yt = !p.per_y && r == ny - 2;
+      if (kWalls && (src_xl || src_xr || src_yb || src_yt)) {
+        for (int dy = -1; dy <= 1; ++dy) {
+          if ((dy == -1 && !src_yb) || (dy == 1 && !src_yt)) continue;
+          if (m + dy < 0 || m + dy >= kTileMid) continue;
+          for (int dx = -1; dx <= 1; ++dx) {
+            if ((dx == -1 && !src_xl) || (dx == 1 && !src_xr)) continue;
+            if (dx == 0 && dy == 0) continue;
+            double ub, vb;
+            wall_velocity(p, c + dx, r + dy, ub, vb);
+            Real sh[kQ];
+            nee_shift(static_cast<double>(rho), static_cast<double>(ux),
+                      static_cast<double>(uy), ub, vb, sh);
+            Real* slotW = tR + (m + dy) * (kQ - 1) * kLanes;
+#pragma unroll
+            for (int q = 1; q < kQ; ++q) slotW[(q - 1) * kLanes + lane + dx] = R[q] + sh[q];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 3: the new state of the wave's output row o (R rows o-2..o+2
+  // are tile rows jout-4 .. jout).
+  {
+    const int o = y0 - kHalo + jout;
+    if (o < y1 && (p.per_y || (o >= 1 && o <= ny - 2))) {
+      Real wyr[kWeightsPerNode];
+      row_weights(weights_y<Real>(p), o, wyr);
+      const Real* rb[5];
+#pragma unroll
+      for (int k2 = 0; k2 < 5; ++k2) rb[k2] = tR + (jout - kHalo + k2) * (kQ - 1) * kLanes + lane;
+      Real out[kQ];
+      out[0] = qout[0];
+#pragma unroll
+      for (int q = 1; q < kQ; ++q) {
+        const int pq = (q - 1) * kLanes;
+        const Real centre = rb[2][pq];
+        Real acc = qout[q];
+        if (ex_of(q) > 0) acc = x_taps<0>(wxr, centre, acc);
+        if (ex_of(q) < 0) acc = x_taps<1>(wxr, centre, acc);
+        if (ey_of(q) != 0) {
+          const int sy = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+          for (int k2 = 0; k2 < kTaps; ++k2) acc += wyr[sy * kTaps + k2] * rb[k2 + sy][pq];
+        }
+        out[q] = acc;
+      }
+      if (lane_o && col_interior) {
+        const unsigned boff =
+            (static_cast<unsigned>(o) * static_cast<unsigned>(pitch) + static_cast<unsigned>(c)) *
+            static_cast<unsigned>(sizeof(Store));
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+          store_state(at_byte(dst + q * plane, boff), Cvt<Store>::st(out[q]));
+      }
+    }
+  }
+  if (kWalls) {
+    __syncthreads();  // the tile's stores are visible to the block
+    piece_walls(p, dst, x0, x1, y0, y1, threadIdx.x, kTileWaves * kLanes);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Single-stencil step: the scheme at A = 0, Guo's T1S2-FDLBM (Remark I).
 // With h = 0 the half-step prediction is the identity (S = P) and the mid-step
 // map returns its input (R = S), so the step is
@@ -1071,10 +1296,28 @@ void launch_single(const StepParams& p, dim3 g, dim3 b, hipStream_t s, bool wall
 }
 
 template <typename Store>
+void launch_tile(const StepParams& p, hipStream_t s, bool walls) {
+  const dim3 g(p.nstrips * ((p.ny + kTileRows - 1) / kTileRows)), b(kTileWaves * kLanes);
+  if (p.has_force) {
+    if (walls)
+      hipLaunchKernelGGL((tile_step_kernel<Store, true, true>), g, b, 0, s, p);
+    else
+      hipLaunchKernelGGL((tile_step_kernel<Store, true, false>), g, b, 0, s, p);
+  } else {
+    if (walls)
+      hipLaunchKernelGGL((tile_step_kernel<Store, false, true>), g, b, 0, s, p);
+    else
+      hipLaunchKernelGGL((tile_step_kernel<Store, false, false>), g, b, 0, s, p);
+  }
+}
+
+template <typename Store>
 hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
   const dim3 g(grid), b(step_threads(kStorageOf<Store>, p.single ? 0 : p.scheme));
   const bool walls = !p.per_x || !p.per_y;
-  if (p.single)
+  if (p.tile)
+    launch_tile<Store>(p, s, walls);
+  else if (p.single)
     launch_single<Store>(p, g, b, s, walls);
   else if (p.scheme == 2)
     launch_fused<Store, 2>(p, g, b, s, walls);

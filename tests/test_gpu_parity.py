@@ -598,3 +598,35 @@ def test_t1s2_fp32_error_vs_oracle():
     err = _rel(np.stack([u, v]), np.stack([ur, vr]))
     print(f"    f32 T1S2: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
     assert err <= 3e-5
+
+
+# ------------------------------ small meshes: the tile kernel (scheme 1)
+
+@pytest.mark.parametrize("kind,storage", [("cavity65", "f64"), ("cavity130x65", "f64"),
+                                          ("cavity130x65", "f32"), ("cavity130x65", "bf16"),
+                                          ("tgv150x70", "f64"), ("poiseuille", "f64"),
+                                          ("cavity5x5", "f64")])
+def test_tile_kernel_is_bitwise_the_march(kind, storage, monkeypatch):
+    """On small meshes the step runs the tile kernel (one block per strip and
+    8 rows, no march); forcing a block count selects the march kernel.  The
+    two give bitwise the same state (walled, ragged, periodic across the
+    seams, forced, 5 x 5; FP64, FP32 and BF16), and the tile kernel's
+    state matches the oracle."""
+    if kind == "cavity65":
+        case = W.cavity_case(64, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
+    elif kind == "cavity130x65":
+        case = _ragged_cavity(0.8)
+    elif kind == "tgv150x70":
+        case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.7, eta=0.05)
+    elif kind == "poiseuille":
+        case = W.poiseuille_case(dt_over_y1=0.9, eta=0.1)
+    else:
+        case = W.cavity_case(4, lid=0.1, re=100.0, cfl=0.5, eta=0.1, noise=1e-4, seed=5)
+    phi0 = oracle.init(case)
+    monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+    _, g_tile, d, u, v = _gpu_run(case, phi0, 60, storage=storage)
+    monkeypatch.setenv("T2S2_BLOCKS", "8")
+    _, g_march, *_ = _gpu_run(case, phi0, 60, storage=storage)
+    assert np.array_equal(g_tile, g_march)
+    if storage == "f64":
+        _compare(case, g_tile, d, u, v, oracle.run(case, phi0, 60))
