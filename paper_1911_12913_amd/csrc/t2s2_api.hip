@@ -174,9 +174,9 @@ struct t2s2_ctx {
   StepParams sp{};
   AuxParams ap{};
   int grid = 0;
-  // The two-stencil kernel's plan of the same step (its own occupancy), for
-  // the adjoint's recompute, which stores S, formed only by step_kernel;
-  // equal to sp unless sp.single.
+  // The two-stencil kernels' plan of the same step (their own occupancy),
+  // for the adjoint's recompute, which stores S, formed only by step_kernel
+  // and tile_step_kernel; equal to sp unless sp.single.
   StepParams sp_gen{};
   int grid_gen = 0;
   // adjoint
@@ -448,10 +448,7 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   if (c->sp.scheme == 1 && !c->sp.single && !std::getenv("T2S2_BLOCKS") &&
       static_cast<long long>(c->sp.nunits) * c->ny < static_cast<long long>(kTileMaxMarchRows) * c->grid)
     c->sp.tile = 1;
-  if (!c->sp.single) {
-    c->sp_gen = c->sp;
-    c->sp_gen.tile = 0;
-  }
+  if (!c->sp.single) c->sp_gen = c->sp;
   if (c->grid < 1 || c->grid_gen < 1) return fail(T2S2_ERR_HIP, "bind: step kernel cannot be resident");
   c->bound = true;
   c->cur = 0;

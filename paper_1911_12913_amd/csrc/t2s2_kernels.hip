@@ -623,14 +623,16 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
 // over a few rows runs four pipelined iterations of three phases each.  Each
 // node takes the expressions of step_kernel.  Wave w forms P of tile rows w
 // and w+8 (rows counted from y0-4) and keeps Q of the one that is an output
-// row (w+8 for w < 4, w otherwise), which it outputs in phase 3.
+// row (w+8 for w < 4, w otherwise), which it outputs in phase 3.  kSaveS is
+// the adjoint's recompute, as in step_kernel (S stored at the interior
+// nodes, the new state's wall nodes not set).
 // ---------------------------------------------------------------------------
 constexpr int kTileRows = 8;
 constexpr int kTileWaves = 8;
 constexpr int kTileIn = kTileRows + 2 * kHalo;   // rows of P
 constexpr int kTileMid = kTileRows + kHalo;      // rows of R
 
-template <typename Store, bool kForce, bool kWalls>
+template <typename Store, bool kForce, bool kWalls, bool kSaveS = false>
 __global__ __launch_bounds__(kTileWaves * kLanes) void tile_step_kernel(StepParams p) {
   using Real = typename Cvt<Store>::R;
   __shared__ Real tP[kTileIn * kQ * kLanes];           // [row][q][lane]
@@ -746,6 +748,14 @@ __global__ __launch_bounds__(kTileWaves * kLanes) void tile_step_kernel(StepPara
       }
       S[q] = q == 0 ? centre : centre + k.A * acc;
     }
+    if (kSaveS && lane_o && col_interior && r >= y0 && r < y1) {
+      Real* sv = static_cast<Real*>(p.save_s);
+      const unsigned boff =
+          (static_cast<unsigned>(r) * static_cast<unsigned>(pitch) + static_cast<unsigned>(c)) *
+          static_cast<unsigned>(sizeof(Real));
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) *at_byte(sv + q * plane, boff) = S[q];
+    }
     double s, jx, jy;
     moment_sums(S, s, jx, jy);
     Real rho, ux, uy;
@@ -832,7 +842,7 @@ __global__ __launch_bounds__(kTileWaves * kLanes) void tile_step_kernel(StepPara
       }
     }
   }
-  if (kWalls) {
+  if (kWalls && !kSaveS) {
     __syncthreads();  // the tile's stores are visible to the block
     piece_walls(p, dst, x0, x1, y0, y1, threadIdx.x, kTileWaves * kLanes);
   }
@@ -1416,6 +1426,14 @@ hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s
 template <typename Store>
 hipError_t launch_step_save_s_t(const StepParams& p, int grid, hipStream_t s) {
   const dim3 g(grid), b(step_threads(kStorageOf<Store>, 1));
+  if (p.tile) {
+    const dim3 gt(p.nstrips * ((p.ny + kTileRows - 1) / kTileRows)), bt(kTileWaves * kLanes);
+    if (!p.per_x || !p.per_y)
+      hipLaunchKernelGGL((tile_step_kernel<Store, false, true, true>), gt, bt, 0, s, p);
+    else
+      hipLaunchKernelGGL((tile_step_kernel<Store, false, false, true>), gt, bt, 0, s, p);
+    return hipGetLastError();
+  }
   if (!p.per_x || !p.per_y)
     hipLaunchKernelGGL((step_kernel<Store, false, true, 1, true>), g, b, 0, s, p);
   else
