@@ -29,6 +29,10 @@
 namespace t2s2 {
 namespace {
 
+// The reverse march takes blocks of eight waves (and half the blocks) when a
+// block of four would have fewer than this many strip-rows.
+constexpr long long kAdjRows8Below = 64;
+
 template <typename Real>
 __device__ inline const Real* wtab_x(const AdjParams& a);
 template <>
@@ -219,26 +223,28 @@ __global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* n
 }
 
 // ---- [5'] .. [1'] in one march down strips of the mesh, with the layout
-// of the fused forward step: 64-lane strips with 56 output columns, four
-// waves, one row each per iteration.
+// of the fused forward step: 64-lane strips with 56 output columns, kRows
+// waves (4, or 8 on small meshes), one row each per iteration.
 //   Phase A, row r = p0 + t: lamR = L^T mu (population 0 none) gathered
 //   from the interior nodes whose stencil reads (c, r) -- x taps as
 //   products w(source) mu(source) formed at the source lane and shifted
 //   in, y taps from the rows around -- then the transpose of the R stage
 //   and of the wall extrapolation of R ([4']: x-wall nodes' lamR from the
 //   neighbouring lane, y-wall rows' gathered on the fly, corners have none);
-//   lamS (zero off the interior) goes to an 8-row LDS ring.
+//   lamS (zero off the interior) goes to an LDS ring of 2 kRows rows.
 //   Phase B, row o = p0 - 2 + t: lamP = [interior] lamS + A L^T lamS from
 //   the ring, lamQ = mu, and lam_n through the P and Q stages.
 // The d/d omega partials sum over the nodes each lane outputs, once each.
-template <typename Store>
-__global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
+template <typename Store, int kRows>
+__global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams a, const Store* g,
                                                  const typename Cvt<Store>::R* mu,
                                                  typename Cvt<Store>::R* lam_out, double* partial,
                                                  int nstrips) {
   using Real = typename Cvt<Store>::R;
-  __shared__ Real ring[kRing * kQ * kLanes];  // lamS: [slot][q][lane]
-  __shared__ double red[256];
+  constexpr int kThreads = kLanes * kRows;
+  constexpr int kSlots = 2 * kRows;  // rows p0-4 .. p0+kRows-1 in use, a power of two
+  __shared__ Real ring[kSlots * kQ * kLanes];  // lamS: [slot][q][lane]
+  __shared__ double red[kThreads];
   const int lane = threadIdx.x & (kLanes - 1);
   const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
   const int nx = a.nx, ny = a.ny;
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
   const Real* WY = wtab_y<Real>(a);
   const Real A = static_cast<Real>(a.A);
   double dw = 0.0;
-  for (int i = threadIdx.x; i < kRing * kQ * kLanes; i += 256) ring[i] = Real(0);
+  for (int i = threadIdx.x; i < kSlots * kQ * kLanes; i += kThreads) ring[i] = Real(0);
 
   // y weight of tap k, sign class sc, of the stencil at source row yi
   // (wave-uniform: read through the constant address space so it becomes a
@@ -308,9 +314,9 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
     for (int k = 0; k < kWeightsPerNode; ++k) wx[k] = in_x ? WX[c * kWeightsPerNode + k] : Real(0);
     __syncthreads();  // ring zero-fill / previous piece complete
 
-    const int niter = (y1 - y0 + 7) / kRowsPerIter;
+    const int niter = (y1 - y0 + 3 + kRows) / kRows;
     for (int it = 0; it < niter; ++it) {
-      const int p0 = y0 - 2 + kRowsPerIter * it;
+      const int p0 = y0 - 2 + kRows * it;
 
       // ---- phase A: lamS of row r
       {
@@ -425,7 +431,7 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
             }
           }
         }
-        Real* slot = ring + (r0 & (kRing - 1)) * kQ * kLanes;
+        Real* slot = ring + (r0 & (kSlots - 1)) * kQ * kLanes;
 #pragma unroll
         for (int q = 0; q < kQ; ++q) slot[q * kLanes + lane] = ls[q];
       }
@@ -443,7 +449,7 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
 #pragma unroll
           for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * plane + ooff]);
           load9(mu, plane, ooff, lq);
-          const Real* cen = ring + (o & (kRing - 1)) * kQ * kLanes + lane;
+          const Real* cen = ring + (o & (kSlots - 1)) * kQ * kLanes + lane;
           // y weights of the taps (zero where the source row is outside a
           // walled axis; the ring holds zero off the interior).
           Real wyo[2][kTaps];
@@ -471,7 +477,7 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
 #pragma unroll
               for (int k = 0; k < kTaps; ++k) {
                 const int yu = o - tap_offset(s, k);  // unwrapped source row
-                acc += wyo[s][k] * ring[(yu & (kRing - 1)) * kQ * kLanes + q * kLanes + lane];
+                acc += wyo[s][k] * ring[(yu & (kSlots - 1)) * kQ * kLanes + q * kLanes + lane];
               }
             }
             lp[q] = (nin ? l : Real(0)) + (q == 0 ? Real(0) : A * acc);
@@ -503,20 +509,23 @@ __global__ __launch_bounds__(256, 2) void adj_strip(AdjParams a, const Store* g,
   }
   red[threadIdx.x] = dw;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// accum += the sum of the n block partials, by one wave: lane l adds
+// partials l, l + 64, ... in that order, then the lanes are summed by the
+// butterfly; the same order on every run.  (One thread walking the partials
+// one at a time waited out a cache round trip per partial.)
 __global__ __launch_bounds__(64) void adj_accumulate(const double* partial, int n,
                                                       double* accum) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < n; ++b) s += partial[b];
-    *accum += s;
-  }
+  double s = 0.0;
+  for (int b = threadIdx.x; b < n; b += kLanes) s += partial[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) *accum += s;
 }
 
 // ---- seed: lam = d(<gu, u> + <gv, v>)/dg at every node.
@@ -603,9 +612,18 @@ hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp,
     mu = static_cast<const Real*>(a.mu);
   }
   const int nstrips = (a.nx + kStripOut - 1) / kStripOut;
-  hipLaunchKernelGGL(adj_strip<Store>, dim3(G), dim3(256), 0, s, a, g, mu,
-                     static_cast<Real*>(lam_n), partial, nstrips);
-  if (accum) hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, G, accum);
+  // Small meshes: half as many blocks of eight waves, so a block marches
+  // twice the rows and fewer of its rows are the two-row halos above and
+  // below its range.
+  const bool rows8 = static_cast<long long>(nstrips) * a.ny < kAdjRows8Below * G;
+  const int Gs = rows8 ? G / 2 : G;
+  if (rows8)
+    hipLaunchKernelGGL((adj_strip<Store, 8>), dim3(Gs), dim3(kLanes * 8), 0, s, a, g, mu,
+                       static_cast<Real*>(lam_n), partial, nstrips);
+  else
+    hipLaunchKernelGGL((adj_strip<Store, 4>), dim3(Gs), dim3(kLanes * 4), 0, s, a, g, mu,
+                       static_cast<Real*>(lam_n), partial, nstrips);
+  if (accum) hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, Gs, accum);
   return hipGetLastError();
 }
 

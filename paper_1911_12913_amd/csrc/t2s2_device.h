@@ -79,6 +79,20 @@ __device__ inline double from_above(double v) {
 __device__ inline float from_below(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
 __device__ inline float from_above(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
 
+// Sum (or max) over the 64 lanes of a wave by a butterfly of lane exchanges
+// (__shfl_xor); every lane ends with the same result (a + b = b + a), formed
+// in the same order on every run.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, kLanes);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v = fmax(v, __shfl_xor(v, m, kLanes));
+  return v;
+}
+
 __device__ inline int wrap(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;

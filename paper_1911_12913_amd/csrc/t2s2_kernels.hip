@@ -1162,20 +1162,6 @@ __global__ __launch_bounds__(256) void moments_kernel(AuxParams a, const Store* 
   }
 }
 
-// Sum (or max) over the 64 lanes of a wave by a butterfly of lane exchanges
-// (__shfl_xor); every lane ends with the same result (a + b = b + a), formed
-// in the same order on every run.
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, kLanes);
-  return v;
-}
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) v = fmax(v, __shfl_xor(v, m, kLanes));
-  return v;
-}
-
 // Deterministic two-pass reduction: fixed grid of kDiagBlocks blocks, each
 // thread accumulates a fixed grid-stride subset, each wave reduces its lanes
 // with wave_sum / wave_max, the block adds its four wave results in wave

@@ -72,11 +72,6 @@ __device__ inline cplx symbol_q(int q, double thx, double thy, double eta) {
   return s;
 }
 
-__device__ inline double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
 // One pass over the (up to two) matrix elements e = lane, lane + 64 of a
 // 9 x 9 matrix.
 template <typename F>
