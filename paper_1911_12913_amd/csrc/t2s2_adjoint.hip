@@ -22,6 +22,7 @@
 // through the pointwise coefficients; its inner products with the adjoints
 // are reduced in a fixed block order.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include "t2s2_device.h"
 #include "t2s2_internal.h"
@@ -29,8 +30,8 @@
 namespace t2s2 {
 namespace {
 
-// The reverse march takes blocks of eight waves (and half the blocks) when a
-// block of four would have fewer than this many strip-rows.
+// The reverse march takes blocks of eight waves when a block of four would
+// have fewer than this many strip-rows.
 constexpr long long kAdjRows8Below = 64;
 
 template <typename Real>
@@ -180,14 +181,34 @@ __device__ inline void load9(const T* base, long long plane, long long off, T v[
 }
 
 // ---- [6'] mu = adjoint of the interior output including the wall rows
-// extrapolated from it; zero on walls.
+// extrapolated from it; zero on walls.  Only the frame of a walled domain
+// differs from lam: the wall nodes and the interior nodes next to a wall
+// (the two outermost rows and columns of each walled axis).  This kernel
+// writes mu there; the reverse march reads mu on the frame and lam
+// everywhere else.
 template <typename Store>
 __global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* next,
                                                       const typename Cvt<Store>::R* lam) {
   using Real = typename Cvt<Store>::R;
   Real* mu = static_cast<Real*>(a.mu);
-  NODE_LOOP(a) {
-    const int x = static_cast<int>(node % a.nx), y = static_cast<int>(node / a.nx);
+  const int nx = a.nx, ny = a.ny;
+  // Rows 0, 1, ny-2, ny-1 (walled y), then columns 0, 1, nx-2, nx-1 of
+  // the other rows (walled x).
+  const long long nrow = a.per_y ? 0 : 4LL * nx;
+  const int r_lo = a.per_y ? 0 : 2, r_hi = a.per_y ? ny : ny - 2;
+  const long long nframe = nrow + (a.per_x ? 0 : 4LL * (r_hi - r_lo));
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < nframe; i += 256LL * gridDim.x) {
+    int x, y;
+    if (i < nrow) {
+      const int k = static_cast<int>(i / nx);
+      x = static_cast<int>(i % nx);
+      y = k < 2 ? k : ny - 4 + k;
+    } else {
+      const long long j = i - nrow;
+      const int k = static_cast<int>(j % 4);
+      y = r_lo + static_cast<int>(j / 4);
+      x = k < 2 ? k : nx - 4 + k;
+    }
     const long long off = static_cast<long long>(y) * a.pitch + x;
     Real m[kQ];
     if (!interior(a, x, y)) {
@@ -235,9 +256,19 @@ __global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* n
 //   Phase B, row o = p0 - 2 + t: lamP = [interior] lamS + A L^T lamS from
 //   the ring, lamQ = mu, and lam_n through the P and Q stages.
 // The d/d omega partials sum over the nodes each lane outputs, once each.
-template <typename Store, int kRows>
-__global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams a, const Store* g,
-                                                 const typename Cvt<Store>::R* mu,
+// Waves per SIMD that the registers of a march variant are budgeted for.
+// The wall paths' FP64 moment algebra holds it at two; a periodic grid
+// compiles without them, so its FP64 four-row blocks fit three per CU and
+// its FP32 ones four (whole blocks of eight waves: two per SIMD each).
+template <typename Store, int kRows, bool kWalls>
+constexpr int adj_waves_per_simd() {
+  return kWalls ? 2 : (sizeof(typename Cvt<Store>::R) == 4 ? 4 : (kRows == 4 ? 3 : 2));
+}
+
+template <typename Store, int kRows, bool kWalls>
+__global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, kWalls>())) void adj_strip(AdjParams a, const Store* g,
+                                                 const typename Cvt<Store>::R* lam,
+                                                 const typename Cvt<Store>::R* muf,
                                                  typename Cvt<Store>::R* lam_out, double* partial,
                                                  int nstrips) {
   using Real = typename Cvt<Store>::R;
@@ -248,6 +279,8 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
   const int lane = threadIdx.x & (kLanes - 1);
   const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
   const int nx = a.nx, ny = a.ny;
+  // A periodic grid (no walled axis) compiles without the wall paths.
+  const bool per_x = !kWalls || a.per_x, per_y = !kWalls || a.per_y;
   const long long plane = a.plane;
   const Real* S = static_cast<const Real*>(a.S);
   const Real* WX = wtab_x<Real>(a);
@@ -259,6 +292,10 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
   // y weight of tap k, sign class sc, of the stencil at source row yi
   // (wave-uniform: read through the constant address space so it becomes a
   // scalar load, which the vector-memory counter does not wait for).
+  // mu at (c, y): from the frame buffer on the frame of a walled domain (the
+  // two outermost rows or columns of a walled axis), from lam elsewhere.
+  auto frame_row = [&](int y) { return !per_y && (y <= 1 || y >= ny - 2); };
+  auto frame_col = [&](int c) { return !per_x && (c <= 1 || c >= nx - 2); };
   using CReal = const __attribute__((address_space(4))) Real*;
   auto ywt = [&](int yi, int sc, int k) {
     const int idx = __builtin_amdgcn_readfirstlane(yi * kWeightsPerNode + sc * kTaps + k);
@@ -273,21 +310,22 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
   // issue together; FP64 skips those loads, which keeps its registers within
   // two waves per SIMD.
   auto lamR_y = [&](int q, int c, int y) {
+    const Real* mcol = frame_col(c) ? muf : lam;
     Real acc = Real(0);
     if (ey_of(q) == 0) return acc;
     const int s = ey_of(q) > 0 ? 0 : 1;
 #pragma unroll
     for (int k = 0; k < kTaps; ++k) {
-      const int yi = along(y, -tap_offset(s, k), ny, a.per_y);
-      const bool rok = yi >= 0 && (a.per_y || (yi >= 1 && yi <= ny - 2));
+      const int yi = along(y, -tap_offset(s, k), ny, per_y);
+      const bool rok = yi >= 0 && (per_y || (yi >= 1 && yi <= ny - 2));
       if constexpr (sizeof(Real) == 8) {
         if (rok)
           acc += WY[yi * kWeightsPerNode + s * kTaps + k] *
-                 mu[q * plane + static_cast<long long>(yi) * a.pitch + c];
+                 (frame_row(yi) ? muf : mcol)[q * plane + static_cast<long long>(yi) * a.pitch + c];
       } else {
         const int yc = rok ? yi : y;
         const Real w = rok ? WY[yc * kWeightsPerNode + s * kTaps + k] : Real(0);
-        acc += w * mu[q * plane + static_cast<long long>(yc) * a.pitch + c];
+        acc += w * (frame_row(yc) ? muf : mcol)[q * plane + static_cast<long long>(yc) * a.pitch + c];
       }
     }
     return acc;
@@ -304,11 +342,12 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
     const int x0 = strip * kStripOut;
     const int x1 = min(x0 + kStripOut, nx);
     const int c0 = x0 - kHalo + lane;  // this lane's column, unwrapped
-    const bool in_x = a.per_x || (c0 >= 0 && c0 < nx);
-    const int c = a.per_x ? wrap(c0, nx) : clampi(c0, 0, nx - 1);
-    const bool col_int = in_x && (a.per_x || (c0 >= 1 && c0 <= nx - 2));
+    const bool in_x = per_x || (c0 >= 0 && c0 < nx);
+    const int c = per_x ? wrap(c0, nx) : clampi(c0, 0, nx - 1);
+    const bool col_int = in_x && (per_x || (c0 >= 1 && c0 <= nx - 2));
     const bool lane_o = lane >= kHalo && lane < kLanes - kHalo && c0 < x1;
-    const bool xl = !a.per_x && c0 == 1, xr = !a.per_x && c0 == nx - 2;
+    const bool xl = !per_x && c0 == 1, xr = !per_x && c0 == nx - 2;
+    const Real* mcol = frame_col(c) ? muf : lam;  // mu of this lane's column off the frame rows
     Real wx[kWeightsPerNode];
 #pragma unroll
     for (int k = 0; k < kWeightsPerNode; ++k) wx[k] = in_x ? WX[c * kWeightsPerNode + k] : Real(0);
@@ -321,13 +360,13 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
       // ---- phase A: lamS of row r
       {
         const int r0 = p0 + t;
-        const bool in_y = a.per_y || (r0 >= 0 && r0 < ny);
+        const bool in_y = per_y || (r0 >= 0 && r0 < ny);
         Real ls[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) ls[q] = Real(0);
         if (in_y) {  // uniform per wave
-          const int r = a.per_y ? wrap(r0, ny) : r0;
-          const bool row_int = a.per_y || (r >= 1 && r <= ny - 2);
+          const int r = per_y ? wrap(r0, ny) : r0;
+          const bool row_int = per_y || (r >= 1 && r <= ny - 2);
           const bool nin = col_int && row_int;
           const long long roff = static_cast<long long>(r) * a.pitch + c;
           // Every load of the phase, issued together before any of it is
@@ -342,20 +381,23 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
           for (int sc = 0; sc < 2; ++sc) {
 #pragma unroll
             for (int k = 0; k < kTaps; ++k) {
-              const int yi = along(r, -tap_offset(sc, k), ny, a.per_y);
-              const bool rok = yi >= 0 && (a.per_y || (yi >= 1 && yi <= ny - 2));
+              const int yi = along(r, -tap_offset(sc, k), ny, per_y);
+              const bool rok = yi >= 0 && (per_y || (yi >= 1 && yi <= ny - 2));
               ysrc[sc][k] = rok ? yi : r;
               wys[sc][k] = rok ? ywt(yi, sc, k) : Real(0);
             }
           }
+          const Real* mr = frame_row(r) ? muf : mcol;
 #pragma unroll
           for (int q = 1; q < kQ; ++q) {
-            mvx[q] = ex_of(q) != 0 ? mu[q * plane + roff] : Real(0);
+            mvx[q] = ex_of(q) != 0 ? mr[q * plane + roff] : Real(0);
             if (ey_of(q) != 0) {
               const int s = ey_of(q) > 0 ? 0 : 1;
 #pragma unroll
-              for (int k = 0; k < kTaps; ++k)
-                myt[q][k] = mu[q * plane + static_cast<long long>(ysrc[s][k]) * a.pitch + c];
+              for (int k = 0; k < kTaps; ++k) {
+                const int ys = ysrc[s][k];
+                myt[q][k] = (frame_row(ys) ? muf : mcol)[q * plane + static_cast<long long>(ys) * a.pitch + c];
+              }
             }
           }
           load9(S, plane, roff, sv);
@@ -387,7 +429,7 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
           // lamR of the x-wall neighbour (its own lane computed it above)
           Real lw[kQ];
           lw[0] = Real(0);
-          if (!a.per_x) {
+          if (!per_x) {
 #pragma unroll
             for (int q = 1; q < kQ; ++q) {
               const Real lo = from_below(lr[q]), hi = from_above(lr[q]);
@@ -408,7 +450,7 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
             };
             if (xl) add_wall(0, r, lw);
             if (xr) add_wall(nx - 1, r, lw);
-            if (!a.per_y && (r == 1 || r == ny - 2)) {
+            if (!per_y && (r == 1 || r == ny - 2)) {
               const int by = r == 1 ? 0 : ny - 1;
               Real lb[kQ];
               lb[0] = Real(0);
@@ -441,14 +483,14 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
       {
         const int o = p0 - 2 + t;
         if (o >= y0 && o < y1) {  // uniform per wave
-          const bool nin = col_int && (a.per_y || (o >= 1 && o <= ny - 2));
+          const bool nin = col_int && (per_y || (o >= 1 && o <= ny - 2));
           // This row's state and mu, loaded before the ring taps so their
           // latency overlaps them.
           const long long ooff = static_cast<long long>(o) * a.pitch + c;
           Real v[kQ], lq[kQ];
 #pragma unroll
           for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * plane + ooff]);
-          load9(mu, plane, ooff, lq);
+          load9(frame_row(o) ? muf : mcol, plane, ooff, lq);
           const Real* cen = ring + (o & (kSlots - 1)) * kQ * kLanes + lane;
           // y weights of the taps (zero where the source row is outside a
           // walled axis; the ring holds zero off the interior).
@@ -457,7 +499,7 @@ __global__ __launch_bounds__(kLanes * kRows, 8 / kRows) void adj_strip(AdjParams
           for (int sc = 0; sc < 2; ++sc) {
 #pragma unroll
             for (int k = 0; k < kTaps; ++k) {
-              const int yi = along(o, -tap_offset(sc, k), ny, a.per_y);
+              const int yi = along(o, -tap_offset(sc, k), ny, per_y);
               wyo[sc][k] = yi >= 0 ? ywt(yi, sc, k) : Real(0);
             }
           }
@@ -593,7 +635,6 @@ hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp,
                           const void* state_n, const void* lam_np1, void* lam_n,
                           double* partial, double* accum, hipStream_t s) {
   using Real = typename Cvt<Store>::R;
-  const int G = kDiagBlocks;  // fixed grid: the reductions are deterministic
   const bool walls = !a.per_x || !a.per_y;
   const Real* mu = static_cast<const Real*>(lam_np1);
   // The step again from state_n, into the scratch state (the walls' adjoint
@@ -605,26 +646,66 @@ hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp,
   hipError_t e = launch_step_save_s(storage, fwd, step_grid, s);
   if (e != hipSuccess) return e;
   const Store* g = static_cast<const Store*>(state_n);
+  // mu on the frame of a walled domain; without walls mu is lam_np1 itself.
+  const Real* muf = mu;
   if (walls) {
-    // Without walls the output adjoint mu is lam_np1 itself.
-    hipLaunchKernelGGL(adj_out_walls<Store>, dim3(G), dim3(256), 0, s, a,
+    const long long nframe = 4LL * (a.nx + a.ny);
+    const int fg = static_cast<int>(std::min<long long>(kDiagBlocks, (nframe + 255) / 256));
+    hipLaunchKernelGGL(adj_out_walls<Store>, dim3(fg), dim3(256), 0, s, a,
                        static_cast<const Store*>(a.next), mu);
-    mu = static_cast<const Real*>(a.mu);
+    muf = static_cast<const Real*>(a.mu);
   }
   const int nstrips = (a.nx + kStripOut - 1) / kStripOut;
-  // Small meshes: half as many blocks of eight waves, so a block marches
-  // twice the rows and fewer of its rows are the two-row halos above and
-  // below its range.
-  const bool rows8 = static_cast<long long>(nstrips) * a.ny < kAdjRows8Below * G;
-  const int Gs = rows8 ? G / 2 : G;
-  if (rows8)
-    hipLaunchKernelGGL((adj_strip<Store, 8>), dim3(Gs), dim3(kLanes * 8), 0, s, a, g, mu,
-                       static_cast<Real*>(lam_n), partial, nstrips);
+  const bool rows8 = a.march_rows8 != 0;
+  const int Gs = a.march_grid;
+  Real* lo = static_cast<Real*>(lam_n);
+  if (rows8 && walls)
+    hipLaunchKernelGGL((adj_strip<Store, 8, true>), dim3(Gs), dim3(kLanes * 8), 0, s, a, g, mu,
+                       muf, lo, partial, nstrips);
+  else if (rows8)
+    hipLaunchKernelGGL((adj_strip<Store, 8, false>), dim3(Gs), dim3(kLanes * 8), 0, s, a, g, mu,
+                       muf, lo, partial, nstrips);
+  else if (walls)
+    hipLaunchKernelGGL((adj_strip<Store, 4, true>), dim3(Gs), dim3(kLanes * 4), 0, s, a, g, mu,
+                       muf, lo, partial, nstrips);
   else
-    hipLaunchKernelGGL((adj_strip<Store, 4>), dim3(Gs), dim3(kLanes * 4), 0, s, a, g, mu,
-                       static_cast<Real*>(lam_n), partial, nstrips);
+    hipLaunchKernelGGL((adj_strip<Store, 4, false>), dim3(Gs), dim3(kLanes * 4), 0, s, a, g, mu,
+                       muf, lo, partial, nstrips);
   if (accum) hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, Gs, accum);
   return hipGetLastError();
+}
+
+template <typename Store, int kRows, bool kWalls>
+hipError_t march_blocks_per_cu(int& n) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_strip<Store, kRows, kWalls>,
+                                                      kLanes * kRows, 0);
+}
+
+// Blocks of the reverse march: as many as are resident at once on the
+// device (two waves per SIMD with walls, three or four on periodic grids,
+// see adj_waves_per_simd).  Small meshes, where a four-wave block would
+// march fewer than kAdjRows8Below strip-rows, take eight-wave blocks: a
+// block then marches twice the rows and fewer of its rows are the two-row
+// halos above and below its range.  The plan is fixed per context, so the
+// order of the d/d omega reduction is too.
+template <typename Store>
+hipError_t plan_march_t(AdjParams& a, int cus) {
+  const bool walls = !a.per_x || !a.per_y;
+  int n4 = 0, n8 = 0;
+  hipError_t e = walls ? march_blocks_per_cu<Store, 4, true>(n4)
+                       : march_blocks_per_cu<Store, 4, false>(n4);
+  if (e == hipSuccess)
+    e = walls ? march_blocks_per_cu<Store, 8, true>(n8) : march_blocks_per_cu<Store, 8, false>(n8);
+  if (e != hipSuccess) return e;
+  auto grid = [&](int per_cu) {
+    const long long g = static_cast<long long>(std::max(per_cu, 1)) * std::max(cus, 1);
+    return static_cast<int>(std::min<long long>(g, kAdjMaxBlocks));
+  };
+  const int g4 = grid(n4);
+  const long long nstrips = (a.nx + kStripOut - 1) / kStripOut;
+  a.march_rows8 = nstrips * a.ny < kAdjRows8Below * g4 ? 1 : 0;
+  a.march_grid = a.march_rows8 ? grid(n8) : g4;
+  return hipSuccess;
 }
 
 }  // namespace
@@ -639,6 +720,11 @@ hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp,
   }
 
 size_t adjoint_real_bytes(int storage) { return storage == kF64 ? 8 : 4; }
+
+hipError_t plan_adjoint_march(int storage, AdjParams& a, int cus) {
+  T2S2_ADJ_DISPATCH(storage, return plan_march_t<Store>(a, cus));
+  return hipSuccess;
+}
 
 hipError_t launch_adjoint_step(int storage, const AdjParams& a, const StepParams& sp,
                                int step_grid, const void* state_n, const void* lam_np1,

@@ -644,7 +644,7 @@ size_t t2s2_adjoint_state_bytes(const t2s2_ctx* c) {
 size_t t2s2_adjoint_scratch_bytes(const t2s2_ctx* c) {
   if (!c) return 0;
   return 2 * align256(t2s2_adjoint_state_bytes(c)) + align256(t2s2_state_bytes(c)) +
-         align256(kDiagBlocks * sizeof(double));
+         align256(kAdjMaxBlocks * sizeof(double));
 }
 
 int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
@@ -689,6 +689,11 @@ int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
   a.mu = p + ab;
   a.next = p + 2 * ab;
   c->adj_partial = reinterpret_cast<double*>(p + 2 * ab + align256(t2s2_state_bytes(c)));
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = plan_adjoint_march(c->cfg.storage, a, cus);
+  if (e != hipSuccess) return hip_fail(e, "bind_adjoint: march plan");
   c->adj_bound = true;
   return T2S2_OK;
 }

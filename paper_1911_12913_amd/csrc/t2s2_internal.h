@@ -142,10 +142,16 @@ struct AdjParams {
   void* S;     // S, from the recompute of the step
   void* mu;    // adjoint of the interior output (= adjoint of Q); walled domains
   void* next;  // f~^{n+1} recomputed (storage type)
+  // Plan of the reverse march (plan_adjoint_march): eight-wave blocks or
+  // four, and the block count (at most kAdjMaxBlocks).
+  int march_rows8;
+  int march_grid;
 };
 
 constexpr int kDiagBlocks = 512;
 constexpr int kDiagSlots = 8;
+// Blocks of the reverse march of the adjoint (one d/d omega partial each).
+constexpr int kAdjMaxBlocks = 1024;
 
 // Launchers (t2s2_kernels.hip).  Return hipError_t of the launch.
 hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s);
@@ -177,6 +183,9 @@ hipError_t launch_copy_probe(const void* src, void* dst, long long plane, int el
 
 // Adjoint launchers (t2s2_adjoint.hip).
 size_t adjoint_real_bytes(int storage);
+// Sets a.march_rows8 and a.march_grid for this mesh, storage and device
+// (cus compute units): as many blocks as fit on the device at once.
+hipError_t plan_adjoint_march(int storage, AdjParams& a, int cus);
 hipError_t launch_adjoint_step(int storage, const AdjParams& a, const StepParams& sp,
                                int step_grid, const void* state_n, const void* lam_np1,
                                void* lam_n, double* partial, double* accum, hipStream_t s);

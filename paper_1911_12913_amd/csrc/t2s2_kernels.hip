@@ -1165,7 +1165,7 @@ __global__ __launch_bounds__(256) void moments_kernel(AuxParams a, const Store* 
 // Deterministic two-pass reduction: fixed grid of kDiagBlocks blocks, each
 // thread accumulates a fixed grid-stride subset, each wave reduces its lanes
 // with wave_sum / wave_max, the block adds its four wave results in wave
-// order, and one final block reduces the partials in block order.
+// order, and one final block reduces the partials in a fixed order.
 template <typename Store>
 __global__ __launch_bounds__(256) void diag_partial_kernel(AuxParams a, const Store* state,
                                                            double* partials) {
@@ -1204,16 +1204,22 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(AuxParams a, const St
   }
 }
 
-__global__ __launch_bounds__(64) void diag_final_kernel(const double* partials, int nblocks,
-                                                        double* result) {
-  const int k = threadIdx.x;
-  if (k < kDiagSlots) {
+// Final pass: wave w reduces slots w, w + 4; lane l takes the partials of
+// blocks l, l + 64, ... in that order, then the butterfly combines the
+// lanes.  The loads of a lane are independent, so they are in flight
+// together (a walk over the blocks one at a time waited out a cache round
+// trip per block).
+__global__ __launch_bounds__(256) void diag_final_kernel(const double* partials, int nblocks,
+                                                         double* result) {
+  const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
+  for (int k = wave; k < kDiagSlots; k += 256 / kLanes) {  // uniform per wave
     double acc = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = lane; b < nblocks; b += kLanes) {
       const double v = partials[b * kDiagSlots + k];
       acc = (k == 2) ? fmax(acc, v) : acc + v;
     }
-    result[k] = acc;
+    acc = k == 2 ? wave_max(acc) : wave_sum(acc);
+    if (lane == 0) result[k] = acc;
   }
 }
 
@@ -1474,7 +1480,7 @@ hipError_t launch_diagnostics(int storage, const AuxParams& a, const void* state
                                    s, a, static_cast<const Store*>(state), partials));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, kDiagBlocks, result);
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partials, kDiagBlocks, result);
   return hipGetLastError();
 }
 
@@ -1486,7 +1492,7 @@ hipError_t launch_velocity_error(int storage, const AuxParams& a, const void* st
                                    s, a, static_cast<const Store*>(state), uref, vref, partials));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, kDiagBlocks, result);
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partials, kDiagBlocks, result);
   return hipGetLastError();
 }
 
