@@ -21,9 +21,12 @@ round-off) and against the closed-form decay of eq 3.4.  A plain copy of
 the nine planes with the step's store policy, over buffers of the state's
 size, gives the practical bandwidth ceiling beside the published peak.
 Guo's T1S2-FDLBM
-(A = 0, the single-stencil kernel) runs last on the same grid in FP64 at
+(A = 0, the single-stencil kernel) runs on the same grid in FP64 at
 CFL 0.25, inside its stable range, for the cost of one scheme against the
-other.
+other.  Last, the differentiation form: the gradient of a probe loss on the
+513 x 513 cavity (2000 steps, sqrt(N) checkpoints) with respect to the
+initial velocity and the viscosity, forward + backward wall time in FP32
+and FP64, and the FP32 gradient against the FP64 one.
 """
 from __future__ import annotations
 
@@ -140,6 +143,67 @@ def copy_ceiling(n, elem_bytes, reps=20, warmup=3):
     return 2 * 9 * n * elem_bytes / (ms * 1e-3) / 1e9
 
 
+def differentiation_leg(nsteps, storages=("f32", "f64"), reps=2):
+    """The differentiation form: lid-driven cavity on the 513 x 513
+    tanh-stretched mesh (c = 1.5), Re 400, CFL 0.9, nsteps steps with
+    sqrt(N) checkpoints; loss = mean over 64 seeded interior probes of
+    |u - u_target|^2 (targets from a run at 1.05 nu); gradient with respect
+    to the initial velocity (seeded Gaussian perturbation, std 1e-3) and nu.
+    Wall time of forward + backward per storage (one untimed run first), and
+    the FP32 gradient against the FP64 one."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1911_12913_amd.rollout import RolloutSpec, T2S2Rollout, forward_velocity
+
+    case = W.cavity_case(512, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=0.0)
+    dev = "cuda:0"
+
+    def t(a):
+        return torch.as_tensor(np.asarray(a), dtype=torch.float64, device=dev)
+
+    probes = W.probe_nodes(case.nx, case.ny, 64, seed=2)
+    pj = torch.as_tensor(probes[:, 1], device=dev)
+    pi = torch.as_tensor(probes[:, 0], device=dev)
+    rho0, zero = t(np.ones((case.ny, case.nx))), t(np.zeros((case.ny, case.nx)))
+    u0, v0 = W.gaussian_velocity(case.nx, case.ny, std=1e-3, seed=1)
+    out, grads = {}, {}
+    for st in storages:
+        spec = RolloutSpec(x=case.x, y=case.y, periodic_x=case.periodic_x,
+                           periodic_y=case.periodic_y, period_x=case.period_x,
+                           period_y=case.period_y, cfl=case.cfl, dt=case.dt or 0.0,
+                           eta=case.eta, A=case.A, u_wall=case.u_wall, storage=st,
+                           nsteps=nsteps, device=dev)
+        ut, vt = forward_velocity(spec, rho0, zero, zero, 1.05 * case.nu)
+        ut, vt = ut[pj, pi].clone(), vt[pj, pi].clone()
+        secs = []
+        for r in range(reps + 1):
+            gu, gv = t(u0).requires_grad_(True), t(v0).requires_grad_(True)
+            gnu = torch.tensor(case.nu, dtype=torch.float64, device=dev, requires_grad=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U, V = T2S2Rollout.apply(rho0, gu, gv, gnu, spec)
+            loss = ((U[pj, pi] - ut) ** 2 + (V[pj, pi] - vt) ** 2).mean()
+            loss.backward()
+            torch.cuda.synchronize()
+            if r > 0:
+                secs.append(time.perf_counter() - t0)
+        grads[st] = (torch.stack([gu.grad, gv.grad]), gnu.grad.item())
+        s_mean = sum(secs) / len(secs)
+        out[st] = {"rollout_s": s_mean, "unit": "s (forward + backward)",
+                   "node_steps_per_s": case.nx * case.ny * nsteps / s_mean,
+                   "checkpoint_every": spec.segment(), "loss": loss.item()}
+    rec = {"workload": f"cavity{case.nx}x{case.ny} stretched c=1.5, Re 400, CFL 0.9, "
+                       f"{nsteps} steps, sqrt(N) checkpoints, 64 probes",
+           "steps": nsteps, "by_storage": out}
+    if "f32" in grads and "f64" in grads:
+        g32, g64 = grads["f32"], grads["f64"]
+        rec["f32_vs_f64_rel_l2_dL_du0"] = rel_l2_dev(g32[0], g64[0])
+        rec["f32_vs_f64_rel_dL_dnu"] = abs(g32[1] - g64[1]) / abs(g64[1])
+    return rec
+
+
 def rel_l2_dev(a, b) -> float:
     import torch
 
@@ -178,6 +242,9 @@ def main(argv=None):
     ap.add_argument("--t1s2-steps", type=int, default=None,
                     help="steps of the FP64 T1S2 (A = 0) line at CFL 0.25 (default: --steps; "
                          "0 = skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="steps of the differentiation-form rollout (513^2 cavity, forward + "
+                         "backward, FP32 and FP64; 0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed region, one plain device copy of this many bytes "
                          "(reference dispatch for scaling rocprofv3 memory counters)")
@@ -256,6 +323,8 @@ def main(argv=None):
                        "kernel": "copy_planes_kernel", "elem_bytes": eb}
     ceiling[args.storage]["step_frac_of_ceiling"] = achieved / ceiling[args.storage]["value"]
 
+    diff = differentiation_leg(args.adjoint_steps) if args.adjoint_steps > 0 else None
+
     cpu = None
     if args.cpu_steps > 0:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
@@ -296,6 +365,7 @@ def main(argv=None):
         "rel_l2_velocity_vs_closed_form": gre,
         "precision_forms": forms,
         "t1s2": t1s2,
+        "differentiation": diff,
         "diagnostics_after": {k: diag[k] for k in ("kinetic_energy", "max_speed", "nonfinite")},
     }
     print(json.dumps(rec), flush=True)
