@@ -220,8 +220,10 @@ size_t t2s2_adjoint_state_bytes(const t2s2_ctx* ctx);
 size_t t2s2_adjoint_scratch_bytes(const t2s2_ctx* ctx);
 
 /* Attach the adjoint scratch (device, 256-byte aligned).  Returns
- * T2S2_ERR_UNSUPPORTED for forced flows and for T2S2_FDLBM2.  No device
- * call. */
+ * T2S2_ERR_UNSUPPORTED for forced flows and for T2S2_FDLBM2.  Plans the
+ * reverse march from the device's compute units and the kernels' occupancy
+ * (blocks of four waves, or eight on small meshes; the environment variable
+ * T2S2_ADJ_ROWS=4 or 8, read here, forces the shape); launches nothing. */
 int t2s2_bind_adjoint(t2s2_ctx* ctx, void* scratch);
 
 /* lambda = d(<gu, u> + <gv, v>)/dg of the velocity of eq 3.3 at every node,

@@ -23,6 +23,7 @@
 // are reduced in a fixed block order.
 #include <hip/hip_runtime.h>
 #include <algorithm>
+#include <cstdlib>
 
 #include "t2s2_device.h"
 #include "t2s2_internal.h"
@@ -704,6 +705,11 @@ hipError_t plan_march_t(AdjParams& a, int cus) {
   const int g4 = grid(n4);
   const long long nstrips = (a.nx + kStripOut - 1) / kStripOut;
   a.march_rows8 = nstrips * a.ny < kAdjRows8Below * g4 ? 1 : 0;
+  // T2S2_ADJ_ROWS=4 or 8 forces the block shape (tests compare the two).
+  if (const char* env = std::getenv("T2S2_ADJ_ROWS")) {
+    if (env[0] == '4' && env[1] == 0) a.march_rows8 = 0;
+    if (env[0] == '8' && env[1] == 0) a.march_rows8 = 1;
+  }
   a.march_grid = a.march_rows8 ? grid(n8) : g4;
   return hipSuccess;
 }

@@ -29,17 +29,39 @@ def _dev(a):
     return torch.as_tensor(np.asarray(a), dtype=torch.float64, device="cuda:0")
 
 
-@pytest.mark.parametrize("kind", ["cavity", "tgv", "cavity_t1s2"])
+def _one_walled_axis(walls_in_x):
+    """Couette channel of 70 x 81 nodes (two strips across): walls on one axis only
+    (tanh-stretched, one wall moving along it), the other axis periodic,
+    so the adjoint's wall frame is rows only or columns only."""
+    case = W.couette_case(nx=70, ny_intervals=80, c=1.5, lid=0.05, nu=0.02, cfl=0.6,
+                          eta=0.1)
+    if walls_in_x:
+        case.x, case.y = case.y.copy(), case.x.copy()
+        case.periodic_x, case.periodic_y = False, True
+        case.period_x, case.period_y = 0.0, 1.0
+        case.u_wall = np.zeros((4, 2))
+        case.u_wall[1, 1] = 0.05
+    n = (case.ny, case.nx)
+    case.rho0 = np.ones(n)
+    case.ux0, case.uy0 = W.gaussian_velocity(case.nx, case.ny, std=1e-3, seed=4)
+    return case
+
+
+@pytest.mark.parametrize("kind", ["cavity", "tgv", "cavity_t1s2", "channel_y_walls",
+                                  "channel_x_walls"])
 def test_adjoint_step_dot_product(kind):
     """<J v, w> = <v, J^T w> for one step: J v by central differences of the
     GPU step, J^T w by the hand-written adjoint step.  At A = 0 the step runs
     the single-stencil kernel and the adjoint's recompute the two-stencil
-    one, so the test also ties the two forward kernels together."""
+    one, so the test also ties the two forward kernels together.  The two
+    channels have walls on one axis only."""
     if kind == "cavity":
         case = W.cavity_case(40, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=1e-3, seed=1)
     elif kind == "cavity_t1s2":
         case = W.cavity_case(40, lid=0.1, re=400.0, cfl=0.25, eta=0.1, noise=1e-3, seed=1)
         case.A = 0.0
+    elif kind.startswith("channel"):
+        case = _one_walled_axis(kind == "channel_x_walls")
     else:
         case = W.tgv_case(48, 40, u0=0.05, nu=0.01, cfl=0.6, eta=0.05)
     print(f"[gpu] adjoint dot product {kind}", flush=True)
@@ -65,6 +87,37 @@ def test_adjoint_step_dot_product(kind):
     lhs, rhs = float(np.sum(jv * w)), float(np.sum(v * jtw))
     print(f"    <Jv,w> {lhs:.12e}  <v,J^T w> {rhs:.12e}", flush=True)
     assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_march_block_shapes_agree(storage, monkeypatch):
+    """The reverse march with blocks of four waves and of eight (forced with
+    T2S2_ADJ_ROWS) gives bitwise the same lambda_n, and dL/domega to
+    round-off (the blocks' partials are summed in another grouping), on a
+    walled cavity, a ragged periodic grid and the two one-walled-axis
+    channels."""
+    cases = [W.cavity_case(200, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=1e-3, seed=3),
+             W.tgv_case(150, 97, u0=0.05, nu=0.01, cfl=0.6, eta=0.05),
+             _one_walled_axis(False), _one_walled_axis(True)]
+    for case in cases:
+        print(f"[gpu] adjoint block shapes {case.name} {case.nx}x{case.ny} {storage}", flush=True)
+        w = W.random_state((9, case.ny, case.nx), 1.0, 23)
+        outs = []
+        for rows in ("4", "8"):
+            monkeypatch.setenv("T2S2_ADJ_ROWS", rows)
+            ctx = t2s2.context_for_case(case, storage=storage)
+            ctx.enable_adjoint()
+            ctx.init_macro(case.rho0, case.ux0, case.uy0)
+            ctx.step(5)
+            state = ctx.save_state()
+            lam_w = ctx.adjoint_load(w)
+            lam_out = ctx.adjoint_buffer()
+            acc = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+            ctx.adjoint_step(state, lam_w, lam_out, acc)
+            outs.append((ctx.adjoint_read(lam_out).cpu().numpy(), float(acc.item())))
+            ctx.close()
+        assert np.array_equal(outs[0][0], outs[1][0])
+        assert abs(outs[0][1] - outs[1][1]) <= 1e-12 * abs(outs[1][1])
 
 
 def test_adjoint_matches_oracle_twin_autograd():
