@@ -240,6 +240,26 @@ int t2s2_adjoint_seed_velocity(t2s2_ctx* ctx, const void* state, const double* g
 int t2s2_adjoint_step(t2s2_ctx* ctx, const void* state_n, const void* lam_np1, void* lam_n,
                       double* domega_accum);
 
+/* One step of the bound scheme from the state buffer src into dst (both of
+ * t2s2_state_bytes(), storage layout), also storing S, the half-step
+ * prediction of eq 2.33, at the interior nodes of s_out
+ * (t2s2_adjoint_state_bytes(), the adjoint's type and layout; its other
+ * entries are left as they are).  dst is the step's new state, wall nodes
+ * included: the state t2s2_step produces (at A = 0 it is formed by the
+ * two-stencil kernel, equal to the single-stencil one's to rounding).  The
+ * three buffers must differ; the bound state buffers are not touched.  Same
+ * scope as the adjoint (unforced, T2S2-FDLBM1 family); needs
+ * t2s2_bind_adjoint.  Asynchronous. */
+int t2s2_step_save_s(t2s2_ctx* ctx, const void* src, void* dst, void* s_out);
+
+/* t2s2_adjoint_step without its recompute of the step: state_np1 and s_n
+ * are dst and s_out of t2s2_step_save_s(ctx, state_n, ...).  Same outputs
+ * as t2s2_adjoint_step (lam_n bitwise equal).  For a backward pass that has
+ * stored each step's S as it recomputed its segment.  Asynchronous. */
+int t2s2_adjoint_step_stored(t2s2_ctx* ctx, const void* state_n, const void* state_np1,
+                             const void* s_n, const void* lam_np1, void* lam_n,
+                             double* domega_accum);
+
 /* Gradients of the equilibrium initial state f~ = f^eq(rho, u) (Sec. 3):
  * grho = dL/drho, gux = dL/dux, guy = dL/duy from lam0 = dL/dg^0.  Device
  * FP64 [ny][nx] fields; outputs may be NULL.  Asynchronous. */

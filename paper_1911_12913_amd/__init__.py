@@ -113,6 +113,8 @@ def load_library(path: str = LIB_PATH):
         "t2s2_bind_adjoint": (i, [vp, vp]),
         "t2s2_adjoint_seed_velocity": (i, [vp, vp, vp, vp, vp]),
         "t2s2_adjoint_step": (i, [vp, vp, vp, vp, vp]),
+        "t2s2_step_save_s": (i, [vp, vp, vp, vp]),
+        "t2s2_adjoint_step_stored": (i, [vp, vp, vp, vp, vp, vp, vp]),
         "t2s2_adjoint_init_macro": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "t2s2_adjoint_read": (i, [vp, vp, vp]),
         "t2s2_adjoint_load": (i, [vp, vp, vp]),
@@ -136,7 +138,8 @@ def exported_symbols() -> Sequence[str]:
             "t2s2_steps_taken", "t2s2_dt", "t2s2_moments", "t2s2_read_distributions",
             "t2s2_diagnostics", "t2s2_velocity_error", "t2s2_stencil_weights", "t2s2_omega", "t2s2_adjoint_state_bytes",
             "t2s2_adjoint_scratch_bytes", "t2s2_bind_adjoint", "t2s2_adjoint_seed_velocity",
-            "t2s2_adjoint_step", "t2s2_adjoint_init_macro", "t2s2_adjoint_read",
+            "t2s2_adjoint_step", "t2s2_step_save_s", "t2s2_adjoint_step_stored",
+            "t2s2_adjoint_init_macro", "t2s2_adjoint_read",
             "t2s2_adjoint_load", "t2s2_stability_map", "t2s2_copy_probe", "t2s2_destroy",
             "t2s2_last_error")
 
@@ -337,6 +340,18 @@ class Context:
         _check(_lib.t2s2_adjoint_step(self._h, state.data_ptr(), lam_np1.data_ptr(),
                                       lam_n.data_ptr(),
                                       domega.data_ptr() if domega is not None else None))
+
+    def step_save_s(self, src, dst, s_out):
+        """One step from the state buffer src into dst, storing S into s_out
+        (an adjoint_buffer())."""
+        _check(_lib.t2s2_step_save_s(self._h, src.data_ptr(), dst.data_ptr(), s_out.data_ptr()))
+
+    def adjoint_step_stored(self, state_n, state_np1, s_n, lam_np1, lam_n, domega=None):
+        """adjoint_step with the step's new state and S from step_save_s."""
+        _check(_lib.t2s2_adjoint_step_stored(
+            self._h, state_n.data_ptr(), state_np1.data_ptr(), s_n.data_ptr(),
+            lam_np1.data_ptr(), lam_n.data_ptr(),
+            domega.data_ptr() if domega is not None else None))
 
     def adjoint_init_macro(self, lam0, rho, ux, uy):
         t = self._torch

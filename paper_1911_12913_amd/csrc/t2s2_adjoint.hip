@@ -631,21 +631,15 @@ int adj_grid(const AdjParams& a) {
   return static_cast<int>(g < 1 ? 1 : (g > kDiagBlocks ? kDiagBlocks : g));
 }
 
+// The reverse stages of the step from state_n, given its S (a.S) and the
+// new state (a.next, whose moments the walls' adjoint needs at the fluid
+// nodes).
 template <typename Store>
-hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp, int step_grid,
-                          const void* state_n, const void* lam_np1, void* lam_n,
-                          double* partial, double* accum, hipStream_t s) {
+hipError_t adjoint_reverse_t(const AdjParams& a, const void* state_n, const void* lam_np1,
+                             void* lam_n, double* partial, double* accum, hipStream_t s) {
   using Real = typename Cvt<Store>::R;
   const bool walls = !a.per_x || !a.per_y;
   const Real* mu = static_cast<const Real*>(lam_np1);
-  // The step again from state_n, into the scratch state (the walls' adjoint
-  // needs its moments at the fluid nodes), storing S as it goes.
-  StepParams fwd = sp;
-  fwd.src = state_n;
-  fwd.dst = a.next;
-  fwd.save_s = a.S;
-  hipError_t e = launch_step_save_s(storage, fwd, step_grid, s);
-  if (e != hipSuccess) return e;
   const Store* g = static_cast<const Store*>(state_n);
   // mu on the frame of a walled domain; without walls mu is lam_np1 itself.
   const Real* muf = mu;
@@ -674,6 +668,21 @@ hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp,
                        muf, lo, partial, nstrips);
   if (accum) hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, Gs, accum);
   return hipGetLastError();
+}
+
+// The step again from state_n into the scratch state, storing S into the
+// scratch as it goes, then the reverse stages.
+template <typename Store>
+hipError_t adjoint_step_t(int storage, const AdjParams& a, const StepParams& sp, int step_grid,
+                          const void* state_n, const void* lam_np1, void* lam_n,
+                          double* partial, double* accum, hipStream_t s) {
+  StepParams fwd = sp;
+  fwd.src = state_n;
+  fwd.dst = a.next;
+  fwd.save_s = a.S;
+  hipError_t e = launch_step_save_s(storage, fwd, step_grid, s);
+  if (e != hipSuccess) return e;
+  return adjoint_reverse_t<Store>(a, state_n, lam_np1, lam_n, partial, accum, s);
 }
 
 template <typename Store, int kRows, bool kWalls>
@@ -737,6 +746,18 @@ hipError_t launch_adjoint_step(int storage, const AdjParams& a, const StepParams
                                void* lam_n, double* partial, double* accum, hipStream_t s) {
   T2S2_ADJ_DISPATCH(storage, return adjoint_step_t<Store>(storage, a, sp, step_grid, state_n,
                                                           lam_np1, lam_n, partial, accum, s));
+  return hipSuccess;
+}
+
+hipError_t launch_adjoint_step_stored(int storage, const AdjParams& a, const void* state_n,
+                                      const void* state_np1, const void* s_n,
+                                      const void* lam_np1, void* lam_n, double* partial,
+                                      double* accum, hipStream_t s) {
+  AdjParams b = a;
+  b.S = const_cast<void*>(s_n);
+  b.next = const_cast<void*>(state_np1);
+  T2S2_ADJ_DISPATCH(storage,
+                    return adjoint_reverse_t<Store>(b, state_n, lam_np1, lam_n, partial, accum, s));
   return hipSuccess;
 }
 

@@ -726,6 +726,34 @@ int t2s2_adjoint_step(t2s2_ctx* c, const void* state_n, const void* lam_np1, voi
   return T2S2_OK;
 }
 
+int t2s2_step_save_s(t2s2_ctx* c, const void* src, void* dst, void* s_out) {
+  g_last_error.clear();
+  if (int rc = adj_ready(c)) return rc;
+  if (!src || !dst || !s_out || src == dst || dst == s_out || src == s_out)
+    return fail(T2S2_ERR_INVALID_ARG, "need three distinct buffers");
+  StepParams fwd = c->sp_gen;
+  fwd.src = src;
+  fwd.dst = dst;
+  fwd.save_s = s_out;
+  hipError_t e = launch_step_save_s(c->cfg.storage, fwd, c->grid_gen, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "step_save_s");
+  return T2S2_OK;
+}
+
+int t2s2_adjoint_step_stored(t2s2_ctx* c, const void* state_n, const void* state_np1,
+                             const void* s_n, const void* lam_np1, void* lam_n,
+                             double* domega_accum) {
+  g_last_error.clear();
+  if (int rc = adj_ready(c)) return rc;
+  if (!state_n || !state_np1 || !s_n || !lam_np1 || !lam_n || lam_np1 == lam_n)
+    return fail(T2S2_ERR_INVALID_ARG, "need the stored step and two distinct adjoint buffers");
+  hipError_t e = launch_adjoint_step_stored(c->cfg.storage, c->adj, state_n, state_np1, s_n,
+                                            lam_np1, lam_n, c->adj_partial, domega_accum,
+                                            c->stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint_step_stored");
+  return T2S2_OK;
+}
+
 int t2s2_adjoint_init_macro(t2s2_ctx* c, const void* lam0, const double* rho, const double* ux,
                             const double* uy, double* grho, double* gux, double* guy) {
   g_last_error.clear();

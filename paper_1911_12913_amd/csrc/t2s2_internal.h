@@ -189,6 +189,12 @@ hipError_t plan_adjoint_march(int storage, AdjParams& a, int cus);
 hipError_t launch_adjoint_step(int storage, const AdjParams& a, const StepParams& sp,
                                int step_grid, const void* state_n, const void* lam_np1,
                                void* lam_n, double* partial, double* accum, hipStream_t s);
+// The reverse stages alone, given S of the step from state_n and the new
+// state state_np1 (from launch_step_save_s).
+hipError_t launch_adjoint_step_stored(int storage, const AdjParams& a, const void* state_n,
+                                      const void* state_np1, const void* s_n,
+                                      const void* lam_np1, void* lam_n, double* partial,
+                                      double* accum, hipStream_t s);
 hipError_t launch_adjoint_seed(int storage, const AdjParams& a, const void* state,
                                const double* gu, const double* gv, void* lam, hipStream_t s);
 hipError_t launch_adjoint_init(int storage, const AdjParams& a, const void* lam,

@@ -607,9 +607,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
       iteration(it + 1, gB, qB, qA);
     }
     __syncthreads();  // the next piece reuses the rings; the piece's stores are visible
-    // The adjoint's recompute reads the new state at interior nodes only.
-    if (kWalls && !kSaveS)
-      piece_walls(p, dst, x0, x1, y0, y1, threadIdx.x % kBlockThreads, kBlockThreads);
+    if (kWalls) piece_walls(p, dst, x0, x1, y0, y1, threadIdx.x % kBlockThreads, kBlockThreads);
   }
 }
 
@@ -623,9 +621,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
 // over a few rows runs four pipelined iterations of three phases each.  Each
 // node takes the expressions of step_kernel.  Wave w forms P of tile rows w
 // and w+8 (rows counted from y0-4) and keeps Q of the one that is an output
-// row (w+8 for w < 4, w otherwise), which it outputs in phase 3.  kSaveS is
-// the adjoint's recompute, as in step_kernel (S stored at the interior
-// nodes, the new state's wall nodes not set).
+// row (w+8 for w < 4, w otherwise), which it outputs in phase 3.  kSaveS
+// also stores S at the interior nodes, as in step_kernel.
 // ---------------------------------------------------------------------------
 constexpr int kTileRows = 8;
 constexpr int kTileWaves = 8;
@@ -842,7 +839,7 @@ __global__ __launch_bounds__(kTileWaves * kLanes) void tile_step_kernel(StepPara
       }
     }
   }
-  if (kWalls && !kSaveS) {
+  if (kWalls) {
     __syncthreads();  // the tile's stores are visible to the block
     piece_walls(p, dst, x0, x1, y0, y1, threadIdx.x, kTileWaves * kLanes);
   }

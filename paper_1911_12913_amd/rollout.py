@@ -5,8 +5,8 @@ state f~ = f^eq(rho0, u0), takes ``spec.nsteps`` steps on the GPU through the
 C-ABI, and returns the final velocity (ux, uy).  Its backward pass runs the
 hand-written discrete adjoint of every step in reverse: the state is stored
 every K = ceil(sqrt(N)) steps during the forward pass, and each segment is
-recomputed from its checkpoint before its adjoint steps run (memory ~2
-sqrt(N) states instead of N).  Gradients: dL/drho0, dL/dux0, dL/duy0 (whole
+recomputed from its checkpoint before its adjoint steps run (memory about
+sqrt(N) checkpoints plus one segment's states and S instead of N states).  Gradients: dL/drho0, dL/dux0, dL/duy0 (whole
 fields) and dL/dnu, with dL/dnu = dL/domega * (-omega / nu) since
 omega = dt / tau and tau = nu / c_s^2 at a fixed dt.
 """
@@ -40,6 +40,12 @@ class RolloutSpec:
     nsteps: int = 1
     checkpoint_every: Optional[int] = None
     device: Any = None
+    # Backward pass: True keeps each step's new state and S while it walks a
+    # segment back (t2s2_step_save_s / t2s2_adjoint_step_stored: one forward
+    # step per time step instead of two); False recomputes the step inside
+    # each adjoint step (memory: two state copies); None chooses True when a
+    # segment's states and S take under a quarter of the free device memory.
+    store_s: Optional[bool] = None
 
     def context(self, nu: float) -> Context:
         cfg = make_config(nu=nu, cfl=self.cfl, dt=self.dt, eta=self.eta, A=self.A,
@@ -96,8 +102,24 @@ class T2S2Rollout(torch.autograd.Function):
         gv = gv if gv is not None else torch.zeros_like(uy0)
         sim.adjoint_seed_velocity(ctx.final_state, gu, gv, lam_a)
         domega = torch.zeros(1, dtype=torch.float64, device=sim.device)
+        store_s = ctx.spec.store_s
+        if store_s is None:
+            seg = ctx.spec.segment() * (ctx.final_state.numel() + lam_a.numel())
+            store_s = seg < torch.cuda.mem_get_info(sim.device)[0] // 4
         for start, saved in reversed(ctx.checkpoints):
             n = min(ctx.spec.segment(), ctx.spec.nsteps - start)
+            if store_s:
+                # states[k + 1] = step(states[k]), with its S in s[k]
+                states, s = [saved], []
+                for k in range(n):
+                    states.append(torch.empty_like(saved))
+                    s.append(sim.adjoint_buffer())
+                    sim.step_save_s(states[k], states[k + 1], s[k])
+                for k in range(n - 1, -1, -1):
+                    sim.adjoint_step_stored(states[k], states[k + 1], s[k], lam_a, lam_b, domega)
+                    lam_a, lam_b = lam_b, lam_a
+                del states, s
+                continue
             sim.restore_state(saved)
             states = [sim.save_state()]
             for _ in range(n - 1):

@@ -126,6 +126,11 @@ def test_calls_on_unbound_context_fail_without_device():
     out = (ctypes.c_double * 3)()
     assert lib.t2s2_velocity_error(h, None, None, out) == t2s2.ERR_NOT_BOUND
     assert lib.t2s2_velocity_error(None, None, None, out) == t2s2.ERR_INVALID_ARG
+    assert lib.t2s2_step_save_s(h, None, None, None) == t2s2.ERR_NOT_BOUND
+    assert lib.t2s2_step_save_s(None, None, None, None) == t2s2.ERR_INVALID_ARG
+    assert lib.t2s2_adjoint_step_stored(h, None, None, None, None, None, None) == t2s2.ERR_NOT_BOUND
+    assert lib.t2s2_adjoint_step_stored(None, None, None, None, None, None,
+                                        None) == t2s2.ERR_INVALID_ARG
     lib.t2s2_destroy(h)
 
 

@@ -120,6 +120,76 @@ def test_adjoint_march_block_shapes_agree(storage, monkeypatch):
         assert abs(outs[0][1] - outs[1][1]) <= 1e-12 * abs(outs[1][1])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("kind", ["cavity", "tgv", "cavity_t1s2"])
+def test_stored_adjoint_step_is_the_recomputing_one(kind, storage):
+    """t2s2_step_save_s gives the state t2s2_step gives (bitwise; at A = 0,
+    where it runs the two-stencil kernel, to rounding), and
+    t2s2_adjoint_step_stored on its outputs gives bitwise the lambda_n and
+    dL/domega of t2s2_adjoint_step."""
+    if kind == "tgv":
+        case = W.tgv_case(48, 40, u0=0.05, nu=0.01, cfl=0.6, eta=0.05)
+    else:
+        case = W.cavity_case(60, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=1e-3, seed=1)
+    if kind == "cavity_t1s2":
+        case.cfl, case.A = 0.25, 0.0
+    print(f"[gpu] stored adjoint step {kind} {storage}", flush=True)
+    ctx = t2s2.context_for_case(case, storage=storage)
+    ctx.enable_adjoint()
+    ctx.init_macro(case.rho0, case.ux0, case.uy0)
+    ctx.step(7)
+    state = ctx.save_state()
+    nxt, s_n = torch.empty_like(state), ctx.adjoint_buffer()
+    ctx.step_save_s(state, nxt, s_n)
+    ctx.step(1)
+    ref = ctx.read_distributions().cpu().numpy()
+    ctx.restore_state(nxt)
+    got = ctx.read_distributions().cpu().numpy()
+    if case.A == 0.0:
+        assert W.rel_l2(got, ref) < (1e-15 if storage == "f64" else 1e-6)
+    else:
+        assert np.array_equal(got, ref)
+    lam_w = ctx.adjoint_load(W.random_state((9, case.ny, case.nx), 1.0, 31))
+    outs = []
+    for stored in (False, True):
+        lam_out = ctx.adjoint_buffer()
+        acc = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        if stored:
+            ctx.adjoint_step_stored(state, nxt, s_n, lam_w, lam_out, acc)
+        else:
+            ctx.adjoint_step(state, lam_w, lam_out, acc)
+        outs.append((ctx.adjoint_read(lam_out).cpu().numpy(), float(acc.item())))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
+    ctx.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_rollout_backward_with_stored_steps(storage):
+    """The rollout's two backward passes (steps and S kept per segment, or
+    the step recomputed inside each adjoint step) give the same gradients:
+    bitwise, since both form every state and S with the same kernels."""
+    case = W.cavity_case(64, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=0.0)
+    print(f"[gpu] rollout backward stored vs recomputed {storage}", flush=True)
+    probes = W.probe_nodes(case.nx, case.ny, 16, seed=2)
+    pj = torch.as_tensor(probes[:, 1], device="cuda:0")
+    pi = torch.as_tensor(probes[:, 0], device="cuda:0")
+    rho0 = _dev(np.ones((case.ny, case.nx)))
+    u0, v0 = W.gaussian_velocity(case.nx, case.ny, std=1e-3, seed=1)
+    grads = []
+    for store in (True, False):
+        spec = _spec(case, 130, storage=storage)
+        spec.store_s = store
+        gu, gv = _dev(u0).requires_grad_(True), _dev(v0).requires_grad_(True)
+        gnu = torch.tensor(case.nu, dtype=torch.float64, device="cuda:0", requires_grad=True)
+        U, V = T2S2Rollout.apply(rho0, gu, gv, gnu, spec)
+        (U[pj, pi] ** 2 + V[pj, pi] ** 2).sum().backward()
+        grads.append((gu.grad.cpu().numpy(), gv.grad.cpu().numpy(), gnu.grad.item()))
+    assert np.array_equal(grads[0][0], grads[1][0])
+    assert np.array_equal(grads[0][1], grads[1][1])
+    assert grads[0][2] == grads[1][2]
+
+
 def test_adjoint_matches_oracle_twin_autograd():
     """Gradients of a probe loss after 40 steps of a 33x33 cavity w.r.t. the
     initial velocity field and nu: GPU adjoint vs autograd through the
