@@ -106,19 +106,22 @@ class T2S2Rollout(torch.autograd.Function):
         if store_s is None:
             seg = ctx.spec.segment() * (ctx.final_state.numel() + lam_a.numel())
             store_s = seg < torch.cuda.mem_get_info(sim.device)[0] // 4
+        if store_s:
+            # one segment's states after its checkpoint and its S, reused
+            K = ctx.spec.segment()
+            seg_states = [torch.empty_like(ctx.final_state) for _ in range(K)]
+            seg_s = [sim.adjoint_buffer() for _ in range(K)]
         for start, saved in reversed(ctx.checkpoints):
             n = min(ctx.spec.segment(), ctx.spec.nsteps - start)
             if store_s:
-                # states[k + 1] = step(states[k]), with its S in s[k]
-                states, s = [saved], []
+                # states[k + 1] = step(states[k]), with its S in seg_s[k]
+                states = [saved] + seg_states[:n]
                 for k in range(n):
-                    states.append(torch.empty_like(saved))
-                    s.append(sim.adjoint_buffer())
-                    sim.step_save_s(states[k], states[k + 1], s[k])
+                    sim.step_save_s(states[k], states[k + 1], seg_s[k])
                 for k in range(n - 1, -1, -1):
-                    sim.adjoint_step_stored(states[k], states[k + 1], s[k], lam_a, lam_b, domega)
+                    sim.adjoint_step_stored(states[k], states[k + 1], seg_s[k], lam_a, lam_b,
+                                            domega)
                     lam_a, lam_b = lam_b, lam_a
-                del states, s
                 continue
             sim.restore_state(saved)
             states = [sim.save_state()]
@@ -129,6 +132,8 @@ class T2S2Rollout(torch.autograd.Function):
                 sim.adjoint_step(states[k], lam_a, lam_b, domega)
                 lam_a, lam_b = lam_b, lam_a
             del states
+        if store_s:
+            del seg_states, seg_s
         grho, gux, guy = sim.adjoint_init_macro(lam_a, rho0, ux0, uy0)
         dnu = domega * (-sim.omega / ctx.nu)
         return grho, gux, guy, dnu.reshape(()).to(torch.float64), None
