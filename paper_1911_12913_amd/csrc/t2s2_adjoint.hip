@@ -11,12 +11,14 @@
 // with L the dt-scaled mixed-difference operator -dt xi . grad.  The
 // adjoint runs [6]..[1] in reverse with the transposed stencil (a gather
 // over the nodes whose stencil reads this one, with their weights) and the
-// transposed moment Jacobians of the equilibrium.  S comes from a recompute
-// of the fused step that stores it as a side output; [6'] (walled domains
-// only; otherwise the output adjoint is lam_{n+1} itself) writes mu node by
-// node; [5'] .. [1'] then run in one kernel that marches down strips of the
-// mesh like the forward step, holding lamS in an LDS ring, so neither lamR
-// nor lamS goes to memory.  The wall-to-fluid scatter of [4] and [6] is
+// transposed moment Jacobians of the equilibrium.  S comes from the fused
+// step run with a side output that stores it (again from state_n, or stored
+// by the caller's earlier such run); [6'] (walled domains only; otherwise
+// the output adjoint is lam_{n+1} itself) writes mu on the frame of wall
+// nodes and their interior neighbours, where alone it differs from
+// lam_{n+1}; [5'] .. [1'] then run in one kernel that marches down strips of
+// the mesh like the forward step, holding lamS in an LDS ring, so neither
+// lamR nor lamS goes to memory.  The wall-to-fluid scatter of [4] and [6] is
 // gathered at the fluid node, so no atomics are needed and the result is
 // deterministic.  d/d omega of the step (omega = dt / tau) enters only
 // through the pointwise coefficients; its inner products with the adjoints
