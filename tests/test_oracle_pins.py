@@ -436,6 +436,69 @@ def test_couette_flow_between_x_walls(vwall):
     assert np.abs(u).max() < 1e-14
 
 
+def _ghost_case(eta, walls_in_x):
+    """Uniform channel, collisionless (nu = inf), A = 0, resting walls on one
+    axis and a periodic other axis."""
+    case = W.couette_case(nx=6, ny_intervals=10, c=0.0, lid=0.0, nu=math.inf, cfl=0.4,
+                          eta=eta, A=0.0)
+    if walls_in_x:
+        case.x, case.y = case.y.copy(), case.x.copy()
+        case.periodic_x, case.periodic_y = False, True
+        case.period_x, case.period_y = 0.0, 1.0
+    return case
+
+
+@pytest.mark.parametrize("walls_in_x", [False, True])
+@pytest.mark.parametrize("eta", [1.0, 0.37])
+def test_wall_adjacent_stencil_takes_the_quadratic_ghost(eta, walls_in_x):
+    """The missing upwind point next to a wall (reading: quadratic ghost
+    f_-1 = 3 f_0 - 3 f_1 + f_2, so the upwind difference of eq 2.38 there
+    equals the central one).  Closed form of one collisionless step at A = 0
+    (P = Q = f~, S = R = P, eq 2.23) from a state whose only non-zero
+    populations are the two moving across the walls, equal to each other and
+    varying across the channel as phi: the momentum is zero everywhere, so
+    the wall extrapolation of eq 3.10 copies the first interior node onto the
+    resting wall (R_0 = R_1).  For the population moving away from the wall
+    at the first interior node, D = (R_2 - R_0)/2 = (phi_2 - phi_1)/2 for
+    every eta; a linear ghost would give (1 - eta)(phi_2 - phi_1)/2.  The
+    population moving toward that wall takes the regular upwind points
+    (j + 1, j + 2).  Both walls, both axes."""
+    case = _ghost_case(eta, walls_in_x)
+    n_across = case.nx if walls_in_x else case.ny
+    rng = np.random.Generator(np.random.PCG64(11))
+    phi = rng.uniform(-1e-3, 1e-3, size=n_across)
+    q_up, q_down = (1, 3) if walls_in_x else (2, 4)   # +xi and -xi across the walls
+    g0 = np.zeros((9, case.ny, case.nx))
+    prof = phi[None, :] if walls_in_x else phi[:, None]
+    g0[q_up] = np.broadcast_to(prof, (case.ny, case.nx))
+    g0[q_down] = g0[q_up]
+    out = oracle.run(case, g0, 1, threads=1)
+    dt = oracle.time_step(case)
+    r = dt / (1.0 / (n_across - 1))   # dt / spacing, uniform mesh
+    p = phi
+
+    def across(a, j):
+        return a[:, j] if walls_in_x else a[j, :]
+
+    # bottom (or left) wall, first interior node j = 1, R_0 = R_1 = phi_1
+    up_exp = p[1] - r * (p[2] - p[1]) / 2
+    down_exp = p[1] + r * ((1 - eta) * (p[2] - p[1]) / 2 - eta * (3 * p[1] - 4 * p[2] + p[3]) / 2)
+    np.testing.assert_allclose(across(out[q_up], 1), up_exp, rtol=0, atol=1e-17)
+    np.testing.assert_allclose(across(out[q_down], 1), down_exp, rtol=0, atol=1e-17)
+    # top (or right) wall, j = n - 2: mirrored, R_{n-1} = R_{n-2}
+    m = n_across - 2
+    down_exp = p[m] + r * (p[m] - p[m - 1]) / 2
+    up_exp = p[m] - r * ((1 - eta) * (p[m] - p[m - 1]) / 2
+                         + eta * (3 * p[m] - 4 * p[m - 1] + p[m - 2]) / 2)
+    np.testing.assert_allclose(across(out[q_down], m), down_exp, rtol=0, atol=1e-17)
+    np.testing.assert_allclose(across(out[q_up], m), up_exp, rtol=0, atol=1e-17)
+    # the regular interior node j = 3 for comparison (no ghost involved)
+    j = 3
+    up_exp = p[j] - r * ((1 - eta) * (p[j + 1] - p[j - 1]) / 2
+                         + eta * (3 * p[j] - 4 * p[j - 1] + p[j - 2]) / 2)
+    np.testing.assert_allclose(across(out[q_up], j), up_exp, rtol=0, atol=1e-17)
+
+
 def test_cavity_mirror_symmetry():
     """A lid moving left gives the mirror image (x -> 1 - x, u -> -u) of a lid
     moving right on the symmetric mesh: the side walls and corners are
