@@ -35,6 +35,8 @@ import hashlib
 import json
 import math
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -87,33 +89,79 @@ def W_tgv_fields(case, t):
     return W.tgv_fields(case.x, case.y, m["k1"], m["k2"], m["u0"], case.nu, t)
 
 
-def gpu_leg(case, storage, steps, warmup, **overrides):
-    """One storage form on the GPU: warmup steps, then `steps` timed steps
-    between two HIP events recorded on the library's launch stream.  Returns
-    the elapsed ms, the diagnostics, dt and the final velocity fields."""
+def timed_windows(ctx, init, steps, warmup, warmup_s, windows):
+    """Untimed steps for warmup_s seconds (clocks settle after an idle
+    period), then the state is initialised again (init(ctx)), warmup
+    untimed steps follow, and `windows` timed windows of exactly `steps`
+    steps, each between two HIP events recorded on the library's launch
+    stream, with a full synchronisation before and after each window.
+    Every run thus takes the same steps from the same initial state.
+    Returns (ms of each window, steps of the time-based warm-up, its
+    seconds)."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    extra = 0
+    chunk = max(1, steps)
+    while time.perf_counter() - t0 < warmup_s:
+        ctx.step(chunk)
+        extra += chunk
+        torch.cuda.synchronize()
+    warm_s = time.perf_counter() - t0
+    init(ctx)
+    ctx.step(warmup)
+    stream = ctx.stream
+    out = []
+    for _ in range(windows):
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        ctx.step(steps)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        out.append(start.elapsed_time(stop))
+    return out, extra, warm_s
+
+
+def gpu_leg(case, storage, steps, warmup, warmup_s=1.0, windows=5, **overrides):
+    """One storage form on the GPU (timed_windows).  Returns the median
+    window's ms, the timing record, the diagnostics, dt and the final
+    velocity fields."""
     import torch
 
     import paper_1911_12913_amd as t2s2
 
     torch.cuda.set_device(0)
     ctx = t2s2.context_for_case(case, storage=storage, device="cuda:0", **overrides)
-    ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
-    ctx.step(warmup)
-    torch.cuda.synchronize()
-    stream = ctx.stream
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    ctx.step(steps)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
+    # The initial fields go to the device once: initialising again from host
+    # arrays idles the GPU for the uploads, and its clocks then take about
+    # 60 steps to return (measured: the first 20-step windows after such an
+    # init ran 0.60, 0.53, 0.51 ms per step against 0.505 ms steady).
+    fields = [torch.as_tensor(a, dtype=torch.float64, device="cuda:0").contiguous()
+              if a is not None else None
+              for a in (case.rho0, case.ux0, case.uy0, case.grad0)]
+
+    def init(c):
+        c.init_macro(*fields)
+
+    init(ctx)
+    wins, extra, warm_s = timed_windows(ctx, init, steps, warmup, warmup_s, windows)
+    ms = statistics.median(wins)
+    timing = {"windows": len(wins), "steps_per_window": steps,
+              "ms_per_step_windows": [w / steps for w in wins],
+              "ms_per_step_median": ms / steps,
+              "spread": (max(wins) - min(wins)) / ms,
+              "warmup_steps": warmup, "warmup_s": warm_s, "warmup_time_steps": extra,
+              "steps_from_init": ctx.steps_taken}
     diag = ctx.diagnostics()
     _, ux, uy = ctx.moments()
     torch.cuda.synchronize()
     dt = ctx.dt
     ctx.close()
-    return ms, diag, dt, torch.stack([ux, uy])
+    del fields
+    return ms, timing, diag, dt, torch.stack([ux, uy])
 
 
 def copy_ceiling(n, elem_bytes, reps=20, warmup=3):
@@ -223,11 +271,116 @@ def cpu_leg(case, steps, threads):
     return (t2 - t1), used
 
 
+def host_cpu():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count(), "affinity": affinity}
+
+
+def configs_leg(threads):
+    """The other workloads of the method, GPU against the oracle: the 32^2
+    Taylor-Green vortex (1000 steps, FP64, the oracle in full), the 257^2
+    cavity (Re 1000, FP64; 5000 GPU steps in captured 100-step graphs, the
+    oracle on a 200-step prefix) and the 2049^2 cavity (Re 5000; 200 GPU
+    steps per storage, the oracle on a 4-step prefix).  MLUPS of each side
+    and, where both ran the same steps, the GPU state against the oracle's."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1911_12913_amd as t2s2
+    import workloads as W
+
+    out = {}
+
+    def gpu_time(case, storage, steps, phi0, graph=False):
+        """MLUPS and ms per step of `steps` steps from phi0 (after as many
+        untimed ones), and the final state."""
+        s = torch.cuda.Stream() if graph else None
+        ctx = t2s2.context_for_case(case, storage=storage, device="cuda:0", stream=s)
+        run = ctx.step
+        if graph:
+            ctx.graph_capture(100)
+            run = ctx.graph_step
+        ctx.init_distributions(torch.from_numpy(phi0))
+        run(steps)
+        ctx.init_distributions(torch.from_numpy(phi0))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(ctx.stream)
+        run(steps)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        g = ctx.read_distributions().cpu().numpy()
+        ctx.close()
+        return case.nx * case.ny * steps / (ms * 1e-3) / 1e6, ms / steps, g
+
+    def oracle_time(case, phi0, steps, nthreads):
+        oracle.set_threads(nthreads)
+        t0 = time.perf_counter()
+        ref = oracle.run(case, phi0, steps, threads=nthreads)
+        secs = time.perf_counter() - t0
+        return case.nx * case.ny * steps / secs / 1e6, secs, ref
+
+    # TGV 32^2: the whole configuration on both sides
+    c1 = W.tgv_case(32, 32, u0=0.01, nu=0.01, cfl=0.5, eta=0.01)
+    phi = oracle.init(c1)
+    gm, gms, g = gpu_time(c1, "f64", 1000, phi)
+    om, osec, ref = oracle_time(c1, phi, 1000, 1)
+    out["tgv32x32"] = {"steps": 1000, "gpu_mlups": gm, "gpu_us_per_step": gms * 1e3,
+                       "oracle_mlups": om, "oracle_threads": 1, "oracle_s": osec,
+                       "rel_l2_gpu_vs_oracle": W.rel_l2(g, ref),
+                       "note": "launch-bound: one 1024-node launch per step"}
+
+    # cavity 257^2: graph-launched GPU steps, oracle prefix
+    c2 = W.cavity_case(256, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
+    phi = oracle.init(c2)
+    gm, gms, _ = gpu_time(c2, "f64", 5000, phi, graph=True)
+    _, _, g = gpu_time(c2, "f64", 200, phi, graph=True)
+    om, osec, ref = oracle_time(c2, phi, 200, threads)
+    out["cavity257x257"] = {"gpu_steps": 5000, "gpu_mlups": gm, "gpu_us_per_step": gms * 1e3,
+                            "launch": "captured 100-step HIP graphs", "oracle_steps": 200,
+                            "oracle_mlups": om, "oracle_threads": threads, "oracle_s": osec,
+                            "rel_l2_gpu_vs_oracle_200_steps": W.rel_l2(g, ref)}
+
+    # cavity 2049^2: FP64 and the precision forms, oracle prefix
+    c4 = W.cavity_case(2048, lid=0.1, re=5000.0, cfl=0.9, eta=0.05, noise=1e-6, seed=0)
+    phi = oracle.init(c4)
+    rec = {"gpu_steps": 200, "by_storage": {}}
+    for st in ("f64", "f32", "bf16", "f16"):
+        gm, gms, _ = gpu_time(c4, st, 200, phi)
+        rec["by_storage"][st] = {"gpu_mlups": gm, "gpu_us_per_step": gms * 1e3}
+    om, osec, ref = oracle_time(c4, phi, 4, threads)
+    _, _, g4 = gpu_time(c4, "f64", 4, phi)
+    rec.update({"oracle_steps": 4, "oracle_mlups": om, "oracle_threads": threads,
+                "oracle_s": osec, "rel_l2_gpu_vs_oracle_4_steps": W.rel_l2(g4, ref)})
+    out["cavity2049x2049"] = rec
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=2000,
+                    help="steps per timed window (each form runs --windows windows)")
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup-s", type=float, default=1.0,
+                    help="after --warmup steps, untimed steps for this many seconds")
+    ap.add_argument("--windows", type=int, default=5,
+                    help="timed windows of --steps steps; the median is reported")
     ap.add_argument("--n", type=int, default=4096, help="grid side")
     ap.add_argument("--storage", default="f64", choices=sorted(BYTES_PER_NODE))
     ap.add_argument("--nu", type=float, default=1e-4)
@@ -245,6 +398,8 @@ def main(argv=None):
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the differentiation-form rollout (513^2 cavity, forward + "
                          "backward, FP32 and FP64; 0 = skip)")
+    ap.add_argument("--configs", type=int, default=1,
+                    help="1: also time the 32^2, 257^2 and 2049^2 workloads against the oracle")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed region, one plain device copy of this many bytes "
                          "(reference dispatch for scaling rocprofv3 memory counters)")
@@ -255,10 +410,16 @@ def main(argv=None):
                           "n_gpus": args.gpus}), flush=True)
         return 2
 
+    def say(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     n, nu, cfl, eta = args.n, args.nu, 0.9, 0.01
     case = tgv_case(n, nu, cfl, eta)
     nodes = n * n
-    ms, diag, dt, vel = gpu_leg(case, args.storage, args.steps, args.warmup)
+    leg = dict(warmup_s=args.warmup_s, windows=args.windows)
+    say(f"tgv{n} {args.storage}: {args.windows} windows of {args.steps} steps")
+    ms, timing, diag, dt, vel = gpu_leg(case, args.storage, args.steps, args.warmup, **leg)
+    say(f"  ms/step windows {['%.4f' % w for w in timing['ms_per_step_windows']]}")
     if args.copy_bytes > 0:
         import torch
 
@@ -278,14 +439,15 @@ def main(argv=None):
     # closed-form velocity (eq 3.4) at the final time, for every form's error
     import torch
 
-    t_end = (args.warmup + args.steps) * dt
+    t_end = timing["steps_from_init"] * dt
     _, ue, ve, _ = W_tgv_fields(case, t_end)
     exact = torch.stack([torch.from_numpy(ue), torch.from_numpy(ve)]).to("cuda:0")
     gre = rel_l2_dev(vel, exact)
 
     forms = {}
     for st in [f for f in args.forms.split(",") if f and f != args.storage]:
-        ms_f, diag_f, _, vel_f = gpu_leg(case, st, args.steps, args.warmup)
+        say(f"tgv{n} {st}")
+        ms_f, tim_f, diag_f, _, vel_f = gpu_leg(case, st, args.steps, args.warmup, **leg)
         v_f = nodes * args.steps / (ms_f * 1e-3) / 1e6
         bl = BYTES_PER_NODE[st] * nodes / (ms_f / args.steps * 1e-3) / 1e9
         forms[st] = {"value": v_f, "unit": "MLUPS", "ms_per_step": ms_f / args.steps,
@@ -293,17 +455,20 @@ def main(argv=None):
                      "rel_l2_velocity_vs_headline": rel_l2_dev(vel_f, vel),
                      "rel_l2_velocity_vs_closed_form": rel_l2_dev(vel_f, exact),
                      "hbm_frac": bl / HBM_PEAK_GBS, "bytes_per_node": BYTES_PER_NODE[st],
-                     "traffic": measured_traffic(st), "nonfinite": diag_f["nonfinite"]}
+                     "traffic": measured_traffic(st), "nonfinite": diag_f["nonfinite"],
+                     "timing": tim_f}
         del vel_f
     del exact
 
     t1s2 = None
     t1s2_steps = args.steps if args.t1s2_steps is None else args.t1s2_steps
     if t1s2_steps > 0:
+        say(f"tgv{n} T1S2 f64")
         case0 = tgv_case(n, nu, 0.25, eta)
-        ms_0, diag_0, dt_0, vel_0 = gpu_leg(case0, "f64", t1s2_steps, args.warmup, A=0.0)
+        ms_0, tim_0, diag_0, dt_0, vel_0 = gpu_leg(case0, "f64", t1s2_steps, args.warmup,
+                                                   A=0.0, **leg)
         v_0 = nodes * t1s2_steps / (ms_0 * 1e-3) / 1e6
-        _, ue0, ve0, _ = W_tgv_fields(case0, (args.warmup + t1s2_steps) * dt_0)
+        _, ue0, ve0, _ = W_tgv_fields(case0, tim_0["steps_from_init"] * dt_0)
         exact0 = torch.stack([torch.from_numpy(ue0), torch.from_numpy(ve0)]).to("cuda:0")
         t1s2 = {"value": v_0, "unit": "MLUPS", "ms_per_step": ms_0 / t1s2_steps,
                 "steps": t1s2_steps, "scheme": "T1S2 (A = 0)", "storage": "f64", "cfl": 0.25,
@@ -312,27 +477,49 @@ def main(argv=None):
                 / HBM_PEAK_GBS,
                 "t2s2_fdlbm1_step_time_ratio": ms_step / (ms_0 / t1s2_steps),
                 "rel_l2_velocity_vs_closed_form": rel_l2_dev(vel_0, exact0),
-                "nonfinite": diag_0["nonfinite"]}
+                "nonfinite": diag_0["nonfinite"], "timing": tim_0}
         del vel_0, exact0
 
+    say("copy ceilings")
     ceiling = {}
-    for st in dict.fromkeys([args.storage, "f32"]):
+    for st in dict.fromkeys([args.storage, "f32", "bf16"]):
         eb = BYTES_PER_NODE[st] // 18
         gbs = copy_ceiling(nodes, eb)
-        ceiling[st] = {"value": gbs, "unit": "GB/s", "frac_of_peak": gbs / HBM_PEAK_GBS,
-                       "kernel": "copy_planes_kernel", "elem_bytes": eb}
-    ceiling[args.storage]["step_frac_of_ceiling"] = achieved / ceiling[args.storage]["value"]
+        ceiling[f"{eb}-byte"] = {"value": gbs, "unit": "GB/s", "frac_of_peak": gbs / HBM_PEAK_GBS,
+                                 "kernel": "copy_planes_kernel", "elem_bytes": eb,
+                                 "storages": [k for k, v in BYTES_PER_NODE.items()
+                                              if v // 18 == eb]}
+    head = ceiling[f"{BYTES_PER_NODE[args.storage] // 18}-byte"]
+    head["step_frac_of_ceiling"] = achieved / head["value"]
+    for st, f in forms.items():
+        c = ceiling.get(f"{BYTES_PER_NODE[st] // 18}-byte")
+        if c:
+            f["frac_of_copy_ceiling"] = f["hbm_frac"] * HBM_PEAK_GBS / c["value"]
 
-    diff = differentiation_leg(args.adjoint_steps) if args.adjoint_steps > 0 else None
+    diff = None
+    if args.adjoint_steps > 0:
+        say("differentiation form")
+        diff = differentiation_leg(args.adjoint_steps)
+
+    cpu_info = host_cpu()
+    # The box allots 16 host CPUs to a one-GPU job; the oracle takes that
+    # share (or fewer, when fewer are available).
+    threads = args.cpu_threads or min(16, cpu_info["affinity"])
+    other = None
+    if args.configs:
+        say("other workloads against the oracle")
+        other = configs_leg(threads)
 
     cpu = None
     if args.cpu_steps > 0:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        say("oracle on the host")
         secs, used = cpu_leg(case, args.cpu_steps, threads)
         cpu = {"value": nodes * args.cpu_steps / secs / 1e6, "unit": "MLUPS", "cores": used,
                "kind": "oracle",
                "sample": f"{args.cpu_steps} FP64 oracle steps of the same {n}x{n} TGV grid "
-                         f"({secs:.1f} s, {used} OpenMP threads)"}
+                         f"({secs:.1f} s, {used} OpenMP threads)",
+               "host": cpu_info,
+               "threads_note": "16 host CPUs are this one-GPU job's share of the box"}
         if args.cpu_single_steps > 0:
             secs1, used1 = cpu_leg(case, args.cpu_single_steps, 1)
             cpu["single_thread"] = {
@@ -356,16 +543,23 @@ def main(argv=None):
         "data": "synthetic (Taylor-Green closed form, eq 3.4/3.5 initial state)",
         "config": {"workload": f"tgv{n}x{n}", "grid": [n, n], "domain": "[0,2pi]^2 periodic",
                    "u0": 0.01, "nu": nu, "cfl": cfl, "eta": eta, "A": 0.5, "dt": dt,
-                   "scheme": "T2S2-FDLBM1", "storage": args.storage},
+                   "scheme": "T2S2-FDLBM1", "storage": args.storage,
+                   "nu_note": "nu = 1e-3 on this grid at CFL 0.9 gives dt/tau = 0.46, where "
+                              "the scheme is unstable for every eta (the oracle and the exact "
+                              "von Neumann model agree); nu = 1e-4 (dt/tau = 4.6) keeps the "
+                              "grid, CFL, precision and work per step"},
+        "timing": timing,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "step_kernel", "bytes_per_node": BYTES_PER_NODE[args.storage]},
+                     "kernel": "step_kernel", "bytes_per_node": BYTES_PER_NODE[args.storage],
+                     "frac_of_copy_ceiling": head["step_frac_of_ceiling"]},
         "copy_ceiling": ceiling,
         "cpu_baseline": cpu,
         "rel_l2_velocity_vs_closed_form": gre,
         "precision_forms": forms,
         "t1s2": t1s2,
         "differentiation": diff,
+        "other_workloads": other,
         "diagnostics_after": {k: diag[k] for k in ("kinetic_energy", "max_speed", "nonfinite")},
     }
     print(json.dumps(rec), flush=True)

@@ -47,7 +47,11 @@ extern "C" {
 #define T2S2_ERR_NOT_BOUND 5
 
 /* Storage of the carried state g = f~ - w.  T2S2_F64 computes in FP64; the
- * reduced forms compute in FP32 with FP64 moment sums. */
+ * reduced forms compute in FP32 with FP64 moment sums.  The state buffers
+ * hold g rounded to nearest even, except T2S2_F16_DEV, which holds
+ * 2^14 g (an exact power-of-two scale, so deviations down to about 4e-9
+ * stay normal FP16 numbers; |g| >= 4 overflows).  The calls that take or
+ * return FP64 fields and distributions convert to and from g. */
 #define T2S2_F64 0
 #define T2S2_F32_DEV 1
 #define T2S2_BF16_DEV 2
@@ -179,19 +183,22 @@ int t2s2_read_distributions(t2s2_ctx* ctx, double* g);
  * out[3] > 0. */
 int t2s2_diagnostics(t2s2_ctx* ctx, double out[T2S2_NDIAG]);
 
-/* Sums for the global relative error of the velocity (eq 3.6) against a
- * reference field u' = (ux_ref, uy_ref): device FP64 arrays [ny][nx]
- * (row-major, no pitch), read only.  out (host) receives
- *   out[0] = sum |u - u'|^2,  out[1] = sum |u'|^2,  out[2] = sum |u|^2
- * over all nodes of the current state, u the velocity of the moments
- * (t2s2_moments).  E(u) of eq 3.6 is sqrt(out[0] / out[1]) for an analytic
- * u'; the residual GRE of the cavity (Sec. 3C) is sqrt(out[0] / out[2])
- * with u' the velocity at the previous output time.  Deterministic
- * reduction; synchronises.  Non-finite populations make the sums
- * non-finite (no error code; t2s2_diagnostics counts them).  Errors:
- * INVALID_ARG (NULL pointer), NOT_BOUND, HIP_ERROR. */
+/* Global relative error of the velocity (eq 3.6) against a reference field
+ * u' = (ux_ref, uy_ref): device FP64 arrays [ny][nx] (row-major, no pitch),
+ * read only.  out (host, T2S2_NGRE doubles) receives, over all nodes of the
+ * current state, u the velocity of the moments (t2s2_moments):
+ *   out[0] = sum |u - u'|^2,  out[1] = sum |u'|^2,  out[2] = sum |u|^2,
+ *   out[3] = sqrt(out[0] / out[1]), E(u) of eq 3.6 for an analytic u'
+ *            (NaN when out[1] = 0),
+ *   out[4] = sqrt(out[0] / out[2]), the residual GRE of the cavity
+ *            (Sec. 3C) when u' is the velocity at the previous output time
+ *            (NaN when out[2] = 0).
+ * Deterministic reduction; synchronises.  Non-finite populations make the
+ * results non-finite (no error code; t2s2_diagnostics counts them).
+ * Errors: INVALID_ARG (NULL pointer), NOT_BOUND, HIP_ERROR. */
+#define T2S2_NGRE 5
 int t2s2_velocity_error(t2s2_ctx* ctx, const double* ux_ref, const double* uy_ref,
-                        double out[3]);
+                        double out[T2S2_NGRE]);
 
 /* Host copies of the stencil weights computed at create: the dt-scaled
  * taps of L = -dt xi_a d/dx_a (the mixed difference of eqs 2.36-2.38, eta
@@ -233,12 +240,14 @@ int t2s2_adjoint_seed_velocity(t2s2_ctx* ctx, const void* state, const double* g
                                const double* gv, void* lam);
 
 /* lam_n = (d f~^{n+1} / d f~^n)^T lam_np1 for the step taken from the
- * state `state_n` (storage layout).  If domega_accum (device, one double) is
- * non-NULL, adds <lam_np1, d f~^{n+1}/d omega> to it; dL/dnu = dL/domega *
- * (-omega / nu).  lam_np1 and lam_n must differ.  Asynchronous;
- * deterministic (fixed reduction order). */
+ * state `state_n` (storage layout).  If dnu_accum (device, one double) is
+ * non-NULL, adds <lam_np1, d f~^{n+1}/d nu> to it, the derivative at a fixed
+ * dt through omega = dt / tau = dt c_s^2 / nu (d omega / d nu = -omega / nu;
+ * zero without collision).  Summed over the steps of a rollout it is dL/dnu.
+ * lam_np1 and lam_n must differ.  Asynchronous; deterministic (fixed
+ * reduction order). */
 int t2s2_adjoint_step(t2s2_ctx* ctx, const void* state_n, const void* lam_np1, void* lam_n,
-                      double* domega_accum);
+                      double* dnu_accum);
 
 /* One step of the bound scheme from the state buffer src into dst (both of
  * t2s2_state_bytes(), storage layout), also storing S, the half-step
@@ -258,7 +267,7 @@ int t2s2_step_save_s(t2s2_ctx* ctx, const void* src, void* dst, void* s_out);
  * stored each step's S as it recomputed its segment.  Asynchronous. */
 int t2s2_adjoint_step_stored(t2s2_ctx* ctx, const void* state_n, const void* state_np1,
                              const void* s_n, const void* lam_np1, void* lam_n,
-                             double* domega_accum);
+                             double* dnu_accum);
 
 /* Gradients of the equilibrium initial state f~ = f^eq(rho, u) (Sec. 3):
  * grho = dL/drho, gux = dL/dux, guy = dL/duy from lam0 = dL/dg^0.  Device

@@ -22,6 +22,8 @@ STORAGE = {"f64": F64, "f32": F32_DEV, "bf16": BF16_DEV, "f16": F16_DEV}
 NDIAG = 6
 DIAG_NAMES = ("mass_excess", "kinetic_energy", "max_speed", "nonfinite", "momentum_x",
               "momentum_y")
+NGRE = 5
+GRE_NAMES = ("sum_diff2", "sum_ref2", "sum_u2", "gre", "residual")
 
 
 class T2S2Error(RuntimeError):
@@ -181,7 +183,17 @@ def make_config(*, nu: float, cfl: float = 0.0, dt: float = 0.0, eta: float = 0.
 
 class Context:
     """Owns a t2s2_ctx and the torch tensors bound to it (two state buffers
-    and the workspace) on one HIP device and stream."""
+    and the workspace) on one HIP device and stream.
+
+    Stream order: the library launches on the bound stream.  Every call
+    below first makes the bound stream wait for the caller's current stream
+    (so inputs written there are complete), and afterwards makes the current
+    stream wait for the bound stream (so returned tensors, and later work on
+    the current stream, see the call's results).  Device tensors handed to
+    the library are marked as used by the bound stream (record_stream), so
+    the caching allocator does not reuse their memory before the bound
+    stream is done with them.  With the two streams the same, this is a
+    no-op."""
 
     def __init__(self, cfg: Config, x, y, device=None, stream=None):
         import numpy as np
@@ -208,8 +220,11 @@ class Context:
             self.state = [torch.empty(nbytes, dtype=torch.uint8, device=self.device)
                           for _ in range(2)]
             self.workspace = torch.empty(wbytes, dtype=torch.uint8, device=self.device)
-            _check(lib.t2s2_bind(h, self.state[0].data_ptr(), self.state[1].data_ptr(),
-                                 self.workspace.data_ptr(), self.stream.cuda_stream))
+            cur = self._enter()
+            rc = lib.t2s2_bind(h, self.state[0].data_ptr(), self.state[1].data_ptr(),
+                               self.workspace.data_ptr(), self.stream.cuda_stream)
+            self._leave(cur, self.state + [self.workspace])
+            _check(rc)
 
     # -- lifetime
     def close(self):
@@ -223,6 +238,33 @@ class Context:
         except Exception:
             pass
 
+    # -- stream order
+    def _enter(self):
+        """Bound stream after the caller's current stream; returns the current
+        stream if it differs from the bound one, else None."""
+        cur = self._torch.cuda.current_stream(self.device)
+        if cur.cuda_stream == self.stream.cuda_stream:
+            return None
+        self.stream.wait_stream(cur)
+        return cur
+
+    def _leave(self, cur, tensors=()):
+        """Current stream after the bound stream; tensors used by the call are
+        recorded as in use on the bound stream."""
+        if cur is None:
+            return
+        for x in tensors:
+            if x is not None:
+                x.record_stream(self.stream)
+        cur.wait_stream(self.stream)
+
+    def _call(self, fn, *args, tensors=()):
+        """One C-ABI call, ordered against the caller's current stream."""
+        cur = self._enter()
+        rc = fn(self._h, *args)
+        self._leave(cur, tensors)
+        _check(rc)
+
     # -- helpers
     def _f64(self, a, shape):
         t = self._torch
@@ -230,6 +272,10 @@ class Context:
         if tuple(a.shape) != tuple(shape):
             raise ValueError(f"expected shape {shape}, got {tuple(a.shape)}")
         return a
+
+    @staticmethod
+    def _ptr(x):
+        return x.data_ptr() if x is not None else None
 
     @property
     def dt(self) -> float:
@@ -248,30 +294,28 @@ class Context:
         shp = (self.ny, self.nx)
         r, u, v = self._f64(rho, shp), self._f64(ux, shp), self._f64(uy, shp)
         g = self._f64(grad, (4,) + shp) if grad is not None else None
-        self._keep = (r, u, v, g)  # alive until the stream has consumed them
-        _check(_lib.t2s2_init_macro(self._h, r.data_ptr(), u.data_ptr(), v.data_ptr(),
-                                    g.data_ptr() if g is not None else None))
+        self._call(_lib.t2s2_init_macro, r.data_ptr(), u.data_ptr(), v.data_ptr(),
+                   self._ptr(g), tensors=(r, u, v, g))
 
     def init_distributions(self, g):
         gd = self._f64(g, (9, self.ny, self.nx))
-        self._keep = (gd,)
-        _check(_lib.t2s2_init_distributions(self._h, gd.data_ptr()))
+        self._call(_lib.t2s2_init_distributions, gd.data_ptr(), tensors=(gd,))
 
     def step(self, n: int = 1):
-        _check(_lib.t2s2_step(self._h, int(n)))
+        self._call(_lib.t2s2_step, int(n))
 
     def graph_capture(self, steps_per_graph: int):
         """Record steps_per_graph (even) steps into a HIP graph; needs the
         context to be bound to a non-default stream."""
-        _check(_lib.t2s2_graph_capture(self._h, int(steps_per_graph)))
+        self._call(_lib.t2s2_graph_capture, int(steps_per_graph))
 
     def graph_step(self, n: int):
-        _check(_lib.t2s2_graph_step(self._h, int(n)))
+        self._call(_lib.t2s2_graph_step, int(n))
 
     def moments(self):
         t = self._torch
         out = [t.empty((self.ny, self.nx), dtype=t.float64, device=self.device) for _ in range(3)]
-        _check(_lib.t2s2_moments(self._h, *[o.data_ptr() for o in out]))
+        self._call(_lib.t2s2_moments, *[o.data_ptr() for o in out], tensors=out)
         return tuple(out)
 
     def velocity_error(self, ux_ref, uy_ref) -> dict:
@@ -285,17 +329,15 @@ class Context:
         for r in refs:
             if tuple(r.shape) != (self.ny, self.nx):
                 raise ValueError(f"reference field must be ({self.ny}, {self.nx})")
-        out = (ctypes.c_double * 3)()
-        _check(_lib.t2s2_velocity_error(self._h, refs[0].data_ptr(), refs[1].data_ptr(), out))
-        d2, r2, u2 = list(out)
-        return {"gre": (d2 / r2) ** 0.5 if r2 > 0 else float("nan"),
-                "residual": (d2 / u2) ** 0.5 if u2 > 0 else float("nan"),
-                "sum_diff2": d2, "sum_ref2": r2, "sum_u2": u2}
+        out = (ctypes.c_double * NGRE)()
+        self._call(_lib.t2s2_velocity_error, refs[0].data_ptr(), refs[1].data_ptr(), out,
+                   tensors=refs)
+        return dict(zip(GRE_NAMES, list(out)))
 
     def read_distributions(self):
         t = self._torch
         g = t.empty((9, self.ny, self.nx), dtype=t.float64, device=self.device)
-        _check(_lib.t2s2_read_distributions(self._h, g.data_ptr()))
+        self._call(_lib.t2s2_read_distributions, g.data_ptr(), tensors=(g,))
         return g
 
     @property
@@ -308,10 +350,23 @@ class Context:
         return self.state[self.current]
 
     def save_state(self):
-        return self.state_tensor().clone()
+        """A copy of the current state buffer, made on the bound stream."""
+        t = self._torch
+        out = t.empty_like(self.state_tensor())
+        cur = self._enter()
+        with t.cuda.stream(self.stream):
+            out.copy_(self.state_tensor())
+        self._leave(cur, (out,))
+        return out
 
-    def restore_state(self, saved, steps_taken: Optional[int] = None):
-        self.state_tensor().copy_(saved)
+    def restore_state(self, saved):
+        """Copy a saved state buffer back into the current one, on the bound
+        stream."""
+        t = self._torch
+        cur = self._enter()
+        with t.cuda.stream(self.stream):
+            self.state_tensor().copy_(saved)
+        self._leave(cur, (saved,))
 
     # -- adjoint
     def enable_adjoint(self):
@@ -320,7 +375,8 @@ class Context:
             t = self._torch
             n = int(_lib.t2s2_adjoint_scratch_bytes(self._h))
             self.adjoint_scratch = t.empty(n, dtype=t.uint8, device=self.device)
-            _check(_lib.t2s2_bind_adjoint(self._h, self.adjoint_scratch.data_ptr()))
+            self._call(_lib.t2s2_bind_adjoint, self.adjoint_scratch.data_ptr(),
+                       tensors=(self.adjoint_scratch,))
 
     def adjoint_buffer(self):
         t = self._torch
@@ -331,54 +387,54 @@ class Context:
         shp = (self.ny, self.nx)
         gu = self._f64(gu, shp) if gu is not None else None
         gv = self._f64(gv, shp) if gv is not None else None
-        self._keep_adj = (gu, gv)
-        _check(_lib.t2s2_adjoint_seed_velocity(
-            self._h, state.data_ptr(), gu.data_ptr() if gu is not None else None,
-            gv.data_ptr() if gv is not None else None, lam.data_ptr()))
+        self._call(_lib.t2s2_adjoint_seed_velocity, state.data_ptr(), self._ptr(gu),
+                   self._ptr(gv), lam.data_ptr(), tensors=(state, gu, gv, lam))
 
-    def adjoint_step(self, state, lam_np1, lam_n, domega=None):
-        _check(_lib.t2s2_adjoint_step(self._h, state.data_ptr(), lam_np1.data_ptr(),
-                                      lam_n.data_ptr(),
-                                      domega.data_ptr() if domega is not None else None))
+    def adjoint_step(self, state, lam_np1, lam_n, dnu=None):
+        """lam_n from lam_np1 through the step taken from `state`; adds the
+        step's contribution to dL/dnu into the device scalar dnu if given."""
+        self._call(_lib.t2s2_adjoint_step, state.data_ptr(), lam_np1.data_ptr(),
+                   lam_n.data_ptr(), self._ptr(dnu), tensors=(state, lam_np1, lam_n, dnu))
 
     def step_save_s(self, src, dst, s_out):
         """One step from the state buffer src into dst, storing S into s_out
         (an adjoint_buffer())."""
-        _check(_lib.t2s2_step_save_s(self._h, src.data_ptr(), dst.data_ptr(), s_out.data_ptr()))
+        self._call(_lib.t2s2_step_save_s, src.data_ptr(), dst.data_ptr(), s_out.data_ptr(),
+                   tensors=(src, dst, s_out))
 
-    def adjoint_step_stored(self, state_n, state_np1, s_n, lam_np1, lam_n, domega=None):
+    def adjoint_step_stored(self, state_n, state_np1, s_n, lam_np1, lam_n, dnu=None):
         """adjoint_step with the step's new state and S from step_save_s."""
-        _check(_lib.t2s2_adjoint_step_stored(
-            self._h, state_n.data_ptr(), state_np1.data_ptr(), s_n.data_ptr(),
-            lam_np1.data_ptr(), lam_n.data_ptr(),
-            domega.data_ptr() if domega is not None else None))
+        self._call(_lib.t2s2_adjoint_step_stored, state_n.data_ptr(), state_np1.data_ptr(),
+                   s_n.data_ptr(), lam_np1.data_ptr(), lam_n.data_ptr(), self._ptr(dnu),
+                   tensors=(state_n, state_np1, s_n, lam_np1, lam_n, dnu))
 
     def adjoint_init_macro(self, lam0, rho, ux, uy):
         t = self._torch
         shp = (self.ny, self.nx)
         r, u, v = self._f64(rho, shp), self._f64(ux, shp), self._f64(uy, shp)
         out = [t.empty(shp, dtype=t.float64, device=self.device) for _ in range(3)]
-        _check(_lib.t2s2_adjoint_init_macro(self._h, lam0.data_ptr(), r.data_ptr(),
-                                            u.data_ptr(), v.data_ptr(),
-                                            *[o.data_ptr() for o in out]))
+        self._call(_lib.t2s2_adjoint_init_macro, lam0.data_ptr(), r.data_ptr(), u.data_ptr(),
+                   v.data_ptr(), *[o.data_ptr() for o in out],
+                   tensors=[lam0, r, u, v] + out)
         return tuple(out)
 
     def adjoint_read(self, lam):
         t = self._torch
         out = t.empty((9, self.ny, self.nx), dtype=t.float64, device=self.device)
-        _check(_lib.t2s2_adjoint_read(self._h, lam.data_ptr(), out.data_ptr()))
+        self._call(_lib.t2s2_adjoint_read, lam.data_ptr(), out.data_ptr(), tensors=(lam, out))
         return out
 
     def adjoint_load(self, dense):
         d = self._f64(dense, (9, self.ny, self.nx))
         lam = self.adjoint_buffer()
-        _check(_lib.t2s2_adjoint_load(self._h, d.data_ptr(), lam.data_ptr()))
-        self._keep_adj = (d,)
+        self._call(_lib.t2s2_adjoint_load, d.data_ptr(), lam.data_ptr(), tensors=(d, lam))
         return lam
 
     def diagnostics(self, raise_nonfinite: bool = True) -> dict:
         out = (ctypes.c_double * NDIAG)()
+        cur = self._enter()
         rc = _lib.t2s2_diagnostics(self._h, out)
+        self._leave(cur)
         if rc != OK and not (rc == ERR_NONFINITE and not raise_nonfinite):
             _check(rc)
         return dict(zip(DIAG_NAMES, list(out)))

@@ -72,73 +72,100 @@ __device__ inline int along(int i, int off, int n, int per) {
 // Offset of tap k for velocity sign class s (0: positive, 1: negative).
 __device__ inline int tap_offset(int s, int k) { return s == 0 ? k - 2 : k - 1; }
 
-// X_q(u) = 3 e + 9/2 e^2 - 3/2 |u|^2 and dX_q/du = (3 + 9 e) xi_q - 3 u.
-__device__ inline double Xq(int q, double ux, double uy) {
-  const double e = ex_of(q) * ux + ey_of(q) * uy;
-  return e * (3.0 + 4.5 * e) - 1.5 * (ux * ux + uy * uy);
+// The moment algebra of the reverse stages runs in the arithmetic type T of
+// the forward step (FP64 for FP64 storage, FP32 otherwise); the moment sums
+// themselves are FP64 in both, as in the forward step.
+
+// 1/x: FP64 from the hardware estimate and two Newton steps, FP32 from the
+// estimate and one.
+__device__ inline double inv(double x) { return recip(x); }
+__device__ inline float inv(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
 }
 
-// Moments rho, u of a node (unforced: u = sum xi g / rho).
+// X_q(u) = 3 e + 9/2 e^2 - 3/2 |u|^2 and dX_q/du = (3 + 9 e) xi_q - 3 u.
 template <typename T>
-__device__ inline void node_rho_u(const T v[kQ], double& rho, double& ux, double& uy) {
+__device__ inline T Xq(int q, T ux, T uy) {
+  const T e = T(ex_of(q)) * ux + T(ey_of(q)) * uy;
+  return e * (T(3) + T(4.5) * e) - T(1.5) * (ux * ux + uy * uy);
+}
+
+// Moments of a node (unforced: u = sum xi g / rho) from FP64 sums, as in
+// the forward step: d = rho - 1 (the sum itself, rounded to T), rho, u.
+template <typename V, typename T>
+__device__ inline void node_rho_u(const V v[kQ], T& d, T& rho, T& ux, T& uy) {
   double s, jx, jy;
   moment_sums(v, s, jx, jy);
-  rho = 1.0 + s;
-  ux = jx / rho;
-  uy = jy / rho;
+  velocity(s, jx, jy, rho, ux, uy);
+  d = static_cast<T>(s);
+}
+
+// f^eq_q - w_q = w_q (d + rho X_q) in the arithmetic type.
+template <typename T>
+__device__ inline void feq_of(T d, T rho, T ux, T uy, T out[kQ]) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) out[q] = T(w_of(q)) * (d + rho * Xq(q, ux, uy));
 }
 
 // Transpose of d(sum_q mu_q F_q)/dg for a pointwise map whose dependence on
 // g goes only through (rho, u): given a = dF/drho . mu and b = dF/du . mu,
 // the gradient is a + b . (xi_q - u) / rho.
-template <typename Real>
-__device__ inline void through_moments(double rho, double ux, double uy, double a, double bx,
-                                       double by, Real out[kQ], bool accumulate) {
-  const double ir = 1.0 / rho;
+template <typename T, typename Real>
+__device__ inline void through_moments(T rho, T ux, T uy, T a, T bx, T by, Real out[kQ],
+                                       bool accumulate) {
+  const T ir = inv(rho);
+  const T cx = bx * ir, cy = by * ir;
+  const T base = a - (cx * ux + cy * uy);
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const double g = a + (bx * (ex_of(q) - ux) + by * (ey_of(q) - uy)) * ir;
+    const T g = base + T(ex_of(q)) * cx + T(ey_of(q)) * cy;
     out[q] = accumulate ? out[q] + static_cast<Real>(g) : static_cast<Real>(g);
   }
 }
 
 // (a, b) for F = feq(rho, u) - w:  dF_q = w_q [(1 + X_q) drho + rho dX_q].
-template <typename Real>
-__device__ inline void feq_ab(double rho, double ux, double uy, const Real mu[kQ], double& a,
-                              double& bx, double& by) {
-  a = 0.0;
-  bx = 0.0;
-  by = 0.0;
+template <typename T, typename Real>
+__device__ inline void feq_ab(T rho, T ux, T uy, const Real mu[kQ], T& a, T& bx, T& by) {
+  a = T(0);
+  bx = T(0);
+  by = T(0);
+  T m3 = T(0);  // sum of w_q mu_q, times 3 u below
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const double m = static_cast<double>(mu[q]) * w_of(q);
-    const double e = ex_of(q) * ux + ey_of(q) * uy;
-    a += m * (1.0 + Xq(q, ux, uy));
-    bx += m * ((3.0 + 9.0 * e) * ex_of(q) - 3.0 * ux);
-    by += m * ((3.0 + 9.0 * e) * ey_of(q) - 3.0 * uy);
+    const T m = static_cast<T>(mu[q]) * T(w_of(q));
+    const T e = T(ex_of(q)) * ux + T(ey_of(q)) * uy;
+    a += m * (T(1) + Xq(q, ux, uy));
+    const T k = m * (T(3) + T(9) * e);
+    if (ex_of(q) != 0) bx += T(ex_of(q)) * k;
+    if (ey_of(q) != 0) by += T(ey_of(q)) * k;
+    m3 += m;
   }
-  bx *= rho;
-  by *= rho;
+  bx = rho * (bx - T(3) * ux * m3);
+  by = rho * (by - T(3) * uy * m3);
 }
 
 // (a, b) for the extrapolation shift F = feq(rho, u_b) - feq(rho, u):
 //   dF_q = w_q [(X_q(u_b) - X_q(u)) drho - rho dX_q(u)].
-template <typename Real>
-__device__ inline void shift_ab(double rho, double ux, double uy, double ub, double vb,
-                                const Real mu[kQ], double& a, double& bx, double& by) {
-  a = 0.0;
-  bx = 0.0;
-  by = 0.0;
+template <typename T, typename Real>
+__device__ inline void shift_ab(T rho, T ux, T uy, T ub, T vb, const Real mu[kQ], T& a, T& bx,
+                                T& by) {
+  a = T(0);
+  bx = T(0);
+  by = T(0);
+  T m3 = T(0);
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const double m = static_cast<double>(mu[q]) * w_of(q);
-    const double e = ex_of(q) * ux + ey_of(q) * uy;
+    const T m = static_cast<T>(mu[q]) * T(w_of(q));
+    const T e = T(ex_of(q)) * ux + T(ey_of(q)) * uy;
     a += m * (Xq(q, ub, vb) - Xq(q, ux, uy));
-    bx -= m * ((3.0 + 9.0 * e) * ex_of(q) - 3.0 * ux);
-    by -= m * ((3.0 + 9.0 * e) * ey_of(q) - 3.0 * uy);
+    const T k = m * (T(3) + T(9) * e);
+    if (ex_of(q) != 0) bx -= T(ex_of(q)) * k;
+    if (ey_of(q) != 0) by -= T(ey_of(q)) * k;
+    m3 += m;
   }
-  bx *= rho;
-  by *= rho;
+  bx = rho * (bx + T(3) * ux * m3);
+  by = rho * (by + T(3) * uy * m3);
 }
 
 __device__ inline void wall_vel(const AdjParams& a, int c, int r, double& ub, double& vb) {
@@ -221,13 +248,13 @@ __global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* n
     }
     load9(lam, a.plane, off, m);
     bool first = true;
-    double rho = 1, ux = 0, uy = 0;
+    Real d = 0, rho = 1, ux = 0, uy = 0;
     for_wall_dependents(a, x, y, [&](int bx, int by) {
       if (first) {
         Real o[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) o[q] = Cvt<Store>::ld(next[q * a.plane + off]);
-        node_rho_u(o, rho, ux, uy);
+        node_rho_u(o, d, rho, ux, uy);
         first = false;
       }
       const long long boff = static_cast<long long>(by) * a.pitch + bx;
@@ -235,8 +262,8 @@ __global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* n
       load9(lam, a.plane, boff, lb);
       double ub, vb;
       wall_vel(a, bx, by, ub, vb);
-      double sa, sbx, sby;
-      shift_ab(rho, ux, uy, ub, vb, lb, sa, sbx, sby);
+      Real sa, sbx, sby;
+      shift_ab(rho, ux, uy, static_cast<Real>(ub), static_cast<Real>(vb), lb, sa, sbx, sby);
 #pragma unroll
       for (int q = 0; q < kQ; ++q) m[q] += lb[q];
       through_moments(rho, ux, uy, sa, sbx, sby, m, true);
@@ -260,12 +287,13 @@ __global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* n
 //   the ring, lamQ = mu, and lam_n through the P and Q stages.
 // The d/d omega partials sum over the nodes each lane outputs, once each.
 // Waves per SIMD that the registers of a march variant are budgeted for.
-// The wall paths' FP64 moment algebra holds it at two; a periodic grid
+// The wall paths hold it at two in FP64 and three in FP32; a periodic grid
 // compiles without them, so its FP64 four-row blocks fit three per CU and
 // its FP32 ones four (whole blocks of eight waves: two per SIMD each).
 template <typename Store, int kRows, bool kWalls>
 constexpr int adj_waves_per_simd() {
-  return kWalls ? 2 : (sizeof(typename Cvt<Store>::R) == 4 ? 4 : (kRows == 4 ? 3 : 2));
+  constexpr bool f32 = sizeof(typename Cvt<Store>::R) == 4;
+  return kWalls ? (f32 && kRows == 4 ? 3 : 2) : (f32 ? 4 : (kRows == 4 ? 3 : 2));
 }
 
 template <typename Store, int kRows, bool kWalls>
@@ -440,13 +468,14 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
             }
           }
           if (nin) {
-            double rho, ux, uy;
-            node_rho_u(sv, rho, ux, uy);
+            Real d, rho, ux, uy;
+            node_rho_u(sv, d, rho, ux, uy);
             auto add_wall = [&](int bx, int by, const Real lb[kQ]) {
               double ub, vb;
               wall_vel(a, bx, by, ub, vb);
-              double sa, sbx, sby;
-              shift_ab(rho, ux, uy, ub, vb, lb, sa, sbx, sby);
+              Real sa, sbx, sby;
+              shift_ab(rho, ux, uy, static_cast<Real>(ub), static_cast<Real>(vb), lb, sa, sbx,
+                       sby);
 #pragma unroll
               for (int q = 0; q < kQ; ++q) lr[q] += lb[q];
               through_moments(rho, ux, uy, sa, sbx, sby, ls, true);
@@ -462,18 +491,20 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
               add_wall(c, by, lb);
             }
             Real feq[kQ];
-            feq_dev(rho - 1.0, rho, ux, uy, feq);
-            double fa, fbx, fby;
+            feq_of(d, rho, ux, uy, feq);
+            Real fa, fbx, fby;
             feq_ab(rho, ux, uy, lr, fa, fbx, fby);
             Real jt[kQ];
-            const double cRe = a.cRe;
+            const Real cRe = static_cast<Real>(a.cRe);
             through_moments(rho, ux, uy, cRe * fa, cRe * fbx, cRe * fby, jt, false);
             const bool own = lane_o && r0 >= y0 && r0 < y1;
+            Real dn = Real(0);  // this node's <lamR, d R / d cRs>
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
               ls[q] += static_cast<Real>(a.cRs) * lr[q] + jt[q];
-              if (own) dw += static_cast<double>(lr[q]) * a.dcRs * static_cast<double>(sv[q] - feq[q]);
+              dn += lr[q] * (sv[q] - feq[q]);
             }
+            if (own) dw += a.dcRs * static_cast<double>(dn);
           }
         }
         Real* slot = ring + (r0 & (kSlots - 1)) * kQ * kLanes;
@@ -527,26 +558,27 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
             }
             lp[q] = (nin ? l : Real(0)) + (q == 0 ? Real(0) : A * acc);
           }
-          double rho, ux, uy;
-          node_rho_u(v, rho, ux, uy);
+          Real d, rho, ux, uy;
+          node_rho_u(v, d, rho, ux, uy);
           Real feq[kQ], mix[kQ];
-          feq_dev(rho - 1.0, rho, ux, uy, feq);
+          feq_of(d, rho, ux, uy, feq);
 #pragma unroll
           for (int q = 0; q < kQ; ++q)
             mix[q] = static_cast<Real>(a.cPe) * lp[q] + static_cast<Real>(a.cQe) * lq[q];
-          double fa, fbx, fby;
+          Real fa, fbx, fby;
           feq_ab(rho, ux, uy, mix, fa, fbx, fby);
           Real out[kQ];
           through_moments(rho, ux, uy, fa, fbx, fby, out, false);
+          Real dp = Real(0), dq = Real(0);  // this node's <lamP, g - feq>, <lamQ, g - feq>
 #pragma unroll
           for (int q = 0; q < kQ; ++q) {
             out[q] += static_cast<Real>(a.cPg) * lp[q] + static_cast<Real>(a.cQg) * lq[q];
-            if (lane_o) {
-              lam_out[q * plane + ooff] = out[q];
-              dw += (a.dcPg * static_cast<double>(lp[q]) + a.dcQg * static_cast<double>(lq[q])) *
-                    static_cast<double>(v[q] - feq[q]);
-            }
+            if (lane_o) lam_out[q * plane + ooff] = out[q];
+            const Real neq = v[q] - feq[q];
+            dp += lp[q] * neq;
+            dq += lq[q] * neq;
           }
+          if (lane_o) dw += a.dcPg * static_cast<double>(dp) + a.dcQg * static_cast<double>(dq);
         }
       }
       __syncthreads();
@@ -561,16 +593,17 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// accum += the sum of the n block partials, by one wave: lane l adds
-// partials l, l + 64, ... in that order, then the lanes are summed by the
-// butterfly; the same order on every run.  (One thread walking the partials
-// one at a time waited out a cache round trip per partial.)
+// accum += scale * (the sum of the n block partials of d/d omega), by one
+// wave: lane l adds partials l, l + 64, ... in that order, then the lanes
+// are summed by the butterfly; the same order on every run.  scale is
+// d omega / d nu, so accum gathers d/d nu.  (One thread walking the
+// partials one at a time waited out a cache round trip per partial.)
 __global__ __launch_bounds__(64) void adj_accumulate(const double* partial, int n,
-                                                      double* accum) {
+                                                      double scale, double* accum) {
   double s = 0.0;
   for (int b = threadIdx.x; b < n; b += kLanes) s += partial[b];
   s = wave_sum(s);
-  if (threadIdx.x == 0) *accum += s;
+  if (threadIdx.x == 0) *accum += s * scale;
 }
 
 // ---- seed: lam = d(<gu, u> + <gv, v>)/dg at every node.
@@ -585,10 +618,11 @@ __global__ __launch_bounds__(256) void adj_seed_velocity(AdjParams a, const Stor
     Real v[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * a.plane + off]);
-    double rho, ux, uy;
-    node_rho_u(v, rho, ux, uy);
+    Real d, rho, ux, uy;
+    node_rho_u(v, d, rho, ux, uy);
     Real out[kQ];
-    through_moments(rho, ux, uy, 0.0, gu ? gu[node] : 0.0, gv ? gv[node] : 0.0, out, false);
+    through_moments(rho, ux, uy, Real(0), static_cast<Real>(gu ? gu[node] : 0.0),
+                    static_cast<Real>(gv ? gv[node] : 0.0), out, false);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) lam[q * a.plane + off] = out[q];
   }
@@ -668,7 +702,9 @@ hipError_t adjoint_reverse_t(const AdjParams& a, const void* state_n, const void
   else
     hipLaunchKernelGGL((adj_strip<Store, 4, false>), dim3(Gs), dim3(kLanes * 4), 0, s, a, g, mu,
                        muf, lo, partial, nstrips);
-  if (accum) hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, Gs, accum);
+  if (accum)
+    hipLaunchKernelGGL(adj_accumulate, dim3(1), dim3(64), 0, s, partial, Gs,
+                       a.dnu_per_domega, accum);
   return hipGetLastError();
 }
 

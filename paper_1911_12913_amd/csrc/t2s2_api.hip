@@ -605,7 +605,7 @@ int t2s2_diagnostics(t2s2_ctx* c, double out[T2S2_NDIAG]) {
 }
 
 int t2s2_velocity_error(t2s2_ctx* c, const double* ux_ref, const double* uy_ref,
-                        double out[3]) {
+                        double out[T2S2_NGRE]) {
   g_last_error.clear();
   if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
   if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
@@ -623,6 +623,10 @@ int t2s2_velocity_error(t2s2_ctx* c, const double* ux_ref, const double* uy_ref,
   out[0] = host[0];
   out[1] = host[1];
   out[2] = host[3];
+  // E(u) of eq 3.6 (normalised by the reference) and the residual form of
+  // Sec. 3C (normalised by the current field).
+  out[3] = host[1] > 0.0 ? std::sqrt(host[0] / host[1]) : NAN;
+  out[4] = host[3] > 0.0 ? std::sqrt(host[0] / host[3]) : NAN;
   return T2S2_OK;
 }
 
@@ -679,6 +683,8 @@ int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
   a.dcPg = -2.0 * (1.0 + A) / ((2.0 + w) * (2.0 + w));
   a.dcQg = -4.0 / ((2.0 + w) * (2.0 + w));
   a.dcRs = -2.0 * A / ((2.0 + A * w) * (2.0 + A * w));
+  // omega = dt / tau = dt c_s^2 / nu at a fixed dt: d omega / d nu = -omega / nu.
+  a.dnu_per_domega = std::isinf(c->cfg.nu) ? 0.0 : -w / c->cfg.nu;
   for (int k = 0; k < 4; ++k) {
     a.uw[k][0] = c->sp.uw[k][0];
     a.uw[k][1] = c->sp.uw[k][1];
@@ -715,13 +721,13 @@ int t2s2_adjoint_seed_velocity(t2s2_ctx* c, const void* state, const double* gu,
 }
 
 int t2s2_adjoint_step(t2s2_ctx* c, const void* state_n, const void* lam_np1, void* lam_n,
-                      double* domega_accum) {
+                      double* dnu_accum) {
   g_last_error.clear();
   if (int rc = adj_ready(c)) return rc;
   if (!state_n || !lam_np1 || !lam_n || lam_np1 == lam_n)
     return fail(T2S2_ERR_INVALID_ARG, "need a state and two distinct adjoint buffers");
   hipError_t e = launch_adjoint_step(c->cfg.storage, c->adj, c->sp_gen, c->grid_gen, state_n, lam_np1,
-                                     lam_n, c->adj_partial, domega_accum, c->stream);
+                                     lam_n, c->adj_partial, dnu_accum, c->stream);
   if (e != hipSuccess) return hip_fail(e, "adjoint_step");
   return T2S2_OK;
 }
@@ -742,13 +748,13 @@ int t2s2_step_save_s(t2s2_ctx* c, const void* src, void* dst, void* s_out) {
 
 int t2s2_adjoint_step_stored(t2s2_ctx* c, const void* state_n, const void* state_np1,
                              const void* s_n, const void* lam_np1, void* lam_n,
-                             double* domega_accum) {
+                             double* dnu_accum) {
   g_last_error.clear();
   if (int rc = adj_ready(c)) return rc;
   if (!state_n || !state_np1 || !s_n || !lam_np1 || !lam_n || lam_np1 == lam_n)
     return fail(T2S2_ERR_INVALID_ARG, "need the stored step and two distinct adjoint buffers");
   hipError_t e = launch_adjoint_step_stored(c->cfg.storage, c->adj, state_n, state_np1, s_n,
-                                            lam_np1, lam_n, c->adj_partial, domega_accum,
+                                            lam_np1, lam_n, c->adj_partial, dnu_accum,
                                             c->stream);
   if (e != hipSuccess) return hip_fail(e, "adjoint_step_stored");
   return T2S2_OK;

@@ -49,11 +49,18 @@ struct Cvt<Bf16> {
     return Bf16{__builtin_bit_cast(unsigned short, static_cast<__bf16>(v))};
   }
 };
+// FP16 holds the deviation times 2^14 (kF16Scale): the multiplications by
+// a power of two are exact, and deviations down to about 4e-9 stay normal
+// FP16 numbers (unscaled, everything below 6.1e-5 would be subnormal, with
+// an absolute spacing of 6e-8, and below 3e-8 zero).  A stored value
+// overflows only for |g| >= 4, far outside a physical state
+// (-w_q < g_q < rho - w_q).
+constexpr float kF16Scale = 16384.0f;
 template <>
 struct Cvt<_Float16> {
   using R = float;
-  __device__ static float ld(_Float16 v) { return static_cast<float>(v); }
-  __device__ static _Float16 st(float v) { return static_cast<_Float16>(v); }  // RNE
+  __device__ static float ld(_Float16 v) { return static_cast<float>(v) * (1.0f / kF16Scale); }
+  __device__ static _Float16 st(float v) { return static_cast<_Float16>(v * kF16Scale); }  // RNE
 };
 
 // Storage code of a storage type.

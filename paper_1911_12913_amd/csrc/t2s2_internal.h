@@ -138,6 +138,7 @@ struct AdjParams {
   double A;
   double cPg, cPe, cQg, cQe, cRs, cRe;
   double dcPg, dcQg, dcRs;  // d/d omega of cPg, cQg, cRs
+  double dnu_per_domega;    // d omega / d nu = -omega / nu at a fixed dt (0 without collision)
   double uw[4][2];
   void* S;     // S, from the recompute of the step
   void* mu;    // adjoint of the interior output (= adjoint of Q); walled domains

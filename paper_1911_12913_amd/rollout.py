@@ -6,9 +6,9 @@ C-ABI, and returns the final velocity (ux, uy).  Its backward pass runs the
 hand-written discrete adjoint of every step in reverse: the state is stored
 every K = ceil(sqrt(N)) steps during the forward pass, and each segment is
 recomputed from its checkpoint before its adjoint steps run (memory about
-sqrt(N) checkpoints plus one segment's states and S instead of N states).  Gradients: dL/drho0, dL/dux0, dL/duy0 (whole
-fields) and dL/dnu, with dL/dnu = dL/domega * (-omega / nu) since
-omega = dt / tau and tau = nu / c_s^2 at a fixed dt.
+sqrt(N) checkpoints plus one segment's states and S instead of N states).
+Gradients: dL/drho0, dL/dux0, dL/duy0 (whole fields) and dL/dnu at a fixed
+dt, which the adjoint steps accumulate on the device.
 """
 from __future__ import annotations
 
@@ -101,7 +101,7 @@ class T2S2Rollout(torch.autograd.Function):
         gu = gu if gu is not None else torch.zeros_like(ux0)
         gv = gv if gv is not None else torch.zeros_like(uy0)
         sim.adjoint_seed_velocity(ctx.final_state, gu, gv, lam_a)
-        domega = torch.zeros(1, dtype=torch.float64, device=sim.device)
+        dnu = torch.zeros(1, dtype=torch.float64, device=sim.device)
         store_s = ctx.spec.store_s
         if store_s is None:
             seg = ctx.spec.segment() * (ctx.final_state.numel() + lam_a.numel())
@@ -120,7 +120,7 @@ class T2S2Rollout(torch.autograd.Function):
                     sim.step_save_s(states[k], states[k + 1], seg_s[k])
                 for k in range(n - 1, -1, -1):
                     sim.adjoint_step_stored(states[k], states[k + 1], seg_s[k], lam_a, lam_b,
-                                            domega)
+                                            dnu)
                     lam_a, lam_b = lam_b, lam_a
                 continue
             sim.restore_state(saved)
@@ -129,11 +129,10 @@ class T2S2Rollout(torch.autograd.Function):
                 sim.step(1)
                 states.append(sim.save_state())
             for k in range(n - 1, -1, -1):
-                sim.adjoint_step(states[k], lam_a, lam_b, domega)
+                sim.adjoint_step(states[k], lam_a, lam_b, dnu)
                 lam_a, lam_b = lam_b, lam_a
             del states
         if store_s:
             del seg_states, seg_s
         grho, gux, guy = sim.adjoint_init_macro(lam_a, rho0, ux0, uy0)
-        dnu = domega * (-sim.omega / ctx.nu)
-        return grho, gux, guy, dnu.reshape(()).to(torch.float64), None
+        return grho, gux, guy, dnu.reshape(()), None

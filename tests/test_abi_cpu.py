@@ -123,7 +123,7 @@ def test_calls_on_unbound_context_fail_without_device():
     assert lib.t2s2_graph_capture(h, 2) == t2s2.ERR_NOT_BOUND
     assert lib.t2s2_graph_step(h, 4) == t2s2.ERR_NOT_BOUND
     assert lib.t2s2_graph_capture(None, 2) == t2s2.ERR_INVALID_ARG
-    out = (ctypes.c_double * 3)()
+    out = (ctypes.c_double * t2s2.NGRE)()
     assert lib.t2s2_velocity_error(h, None, None, out) == t2s2.ERR_NOT_BOUND
     assert lib.t2s2_velocity_error(None, None, None, out) == t2s2.ERR_INVALID_ARG
     assert lib.t2s2_step_save_s(h, None, None, None) == t2s2.ERR_NOT_BOUND

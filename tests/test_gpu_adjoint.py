@@ -89,10 +89,90 @@ def test_adjoint_step_dot_product(kind):
     assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
 
 
+@pytest.mark.parametrize("kind", ["cavity", "tgv", "channel_y_walls", "channel_x_walls"])
+def test_fp32_adjoint_step_dot_product(kind):
+    """<J v, w> = <v, J^T w> for one FP32-storage step (FP32 arithmetic, FP64
+    moment sums): J v by central differences of the GPU step, taken along
+    the perturbation that survives the rounding of the two perturbed states
+    to FP32 (read back from the library), J^T w by the FP32 adjoint step.
+    The difference quotient of an FP32 map carries FP32 rounding of the two
+    stepped states over 2 eps (about 3e-5 of the product here, where the
+    FP32 J^T w itself is within 1e-5 of the FP64 one), hence 1e-4."""
+    if kind == "cavity":
+        case = W.cavity_case(40, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=1e-3, seed=1)
+    elif kind.startswith("channel"):
+        case = _one_walled_axis(kind == "channel_x_walls")
+    else:
+        case = W.tgv_case(48, 40, u0=0.05, nu=0.01, cfl=0.6, eta=0.05)
+    print(f"[gpu] fp32 adjoint dot product {kind}", flush=True)
+    ctx = t2s2.context_for_case(case, storage="f32")
+    ctx.enable_adjoint()
+    g0 = oracle.run(case, oracle.init(case), 20)
+    v = W.random_state(g0.shape, 1.0, 21)
+    w = W.random_state(g0.shape, 1.0, 22)
+    eps = 1e-3 * np.abs(g0).max()
+
+    def load(g):
+        ctx.init_distributions(torch.from_numpy(g))
+        return ctx.read_distributions().cpu().numpy()  # as stored (FP32)
+
+    def step_from(g):
+        ctx.init_distributions(torch.from_numpy(g))
+        ctx.step(1)
+        return ctx.read_distributions().cpu().numpy()
+
+    gp, gm = load(g0 + eps * v), load(g0 - eps * v)
+    dv = (gp - gm) / (2 * eps)
+    jv = (step_from(gp) - step_from(gm)) / (2 * eps)
+    ctx.init_distributions(torch.from_numpy(g0))
+    state = ctx.save_state()
+    lam_w = ctx.adjoint_load(w)
+    lam_out = ctx.adjoint_buffer()
+    ctx.adjoint_step(state, lam_w, lam_out)
+    jtw = ctx.adjoint_read(lam_out).cpu().numpy()
+    w32 = ctx.adjoint_read(lam_w).cpu().numpy()  # w as the FP32 adjoint holds it
+    lhs, rhs = float(np.sum(jv * w32)), float(np.sum(dv * jtw))
+    print(f"    <Jv,w> {lhs:.9e}  <v,J^T w> {rhs:.9e}  rel {abs(lhs - rhs) / abs(rhs):.2e}",
+          flush=True)
+    assert abs(lhs - rhs) <= 1e-4 * abs(rhs)
+
+
+@pytest.mark.parametrize("kind", ["cavity", "tgv", "channel_y_walls", "channel_x_walls"])
+def test_fp32_adjoint_step_matches_fp64_adjoint_step(kind):
+    """The FP32 adjoint step (its stages' algebra in FP32) against the FP64
+    one on the same state and adjoint (both exactly representable in FP32):
+    lambda_n and the step's dL/dnu agree to FP32 rounding."""
+    if kind == "cavity":
+        case = W.cavity_case(60, lid=0.1, re=400.0, cfl=0.9, eta=0.1, noise=1e-3, seed=1)
+    elif kind.startswith("channel"):
+        case = _one_walled_axis(kind == "channel_x_walls")
+    else:
+        case = W.tgv_case(150, 97, u0=0.05, nu=0.01, cfl=0.6, eta=0.05)
+    print(f"[gpu] fp32 vs fp64 adjoint step {kind}", flush=True)
+    g0 = oracle.run(case, oracle.init(case), 15).astype(np.float32).astype(np.float64)
+    w = W.random_state(g0.shape, 1.0, 24).astype(np.float32).astype(np.float64)
+    outs = {}
+    for storage in ("f64", "f32"):
+        ctx = t2s2.context_for_case(case, storage=storage)
+        ctx.enable_adjoint()
+        ctx.init_distributions(torch.from_numpy(g0))
+        state = ctx.save_state()
+        lam_w = ctx.adjoint_load(w)
+        lam_out = ctx.adjoint_buffer()
+        acc = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        ctx.adjoint_step(state, lam_w, lam_out, acc)
+        outs[storage] = (ctx.adjoint_read(lam_out).cpu().numpy(), float(acc.item()))
+        ctx.close()
+    e_l = W.rel_l2(outs["f32"][0], outs["f64"][0])
+    e_nu = abs(outs["f32"][1] - outs["f64"][1]) / abs(outs["f64"][1])
+    print(f"    lambda_n rel L2 {e_l:.2e}  dL/dnu rel {e_nu:.2e}", flush=True)
+    assert e_l < 1e-5 and e_nu < 1e-3
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_adjoint_march_block_shapes_agree(storage, monkeypatch):
     """The reverse march with blocks of four waves and of eight (forced with
-    T2S2_ADJ_ROWS) gives bitwise the same lambda_n, and dL/domega to
+    T2S2_ADJ_ROWS) gives bitwise the same lambda_n, and dL/dnu to
     round-off (the blocks' partials are summed in another grouping), on a
     walled cavity, a ragged periodic grid and the two one-walled-axis
     channels."""
@@ -126,7 +206,7 @@ def test_stored_adjoint_step_is_the_recomputing_one(kind, storage):
     """t2s2_step_save_s gives the state t2s2_step gives (bitwise; at A = 0,
     where it runs the two-stencil kernel, to rounding), and
     t2s2_adjoint_step_stored on its outputs gives bitwise the lambda_n and
-    dL/domega of t2s2_adjoint_step."""
+    dL/dnu of t2s2_adjoint_step."""
     if kind == "tgv":
         case = W.tgv_case(48, 40, u0=0.05, nu=0.01, cfl=0.6, eta=0.05)
     else:
@@ -322,7 +402,9 @@ def test_fp32_adjoint_against_fp64_adjoint(nsteps):
     e_nu = abs(grads["f32"][2] - grads["f64"][2]) / abs(grads["f64"][2])
     print(f"    FP32 vs FP64 adjoint, {nsteps} steps: dL/du0 rel L2 {e_u:.2e}, "
           f"dL/dnu rel {e_nu:.2e}", flush=True)
-    assert e_u < 1e-2 and e_nu < 1e-2
+    # the FP32 forward trajectory itself drifts from the FP64 one with N
+    tol = 1e-3 if nsteps <= 200 else 1e-2
+    assert e_u < tol and e_nu < tol
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])

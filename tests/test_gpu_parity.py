@@ -39,15 +39,27 @@ def _gpu_run(case, phi0, nsteps, storage="f64", **kw):
     return ctx, g, d, u, v
 
 
+def _max_rel(a, b):
+    """Largest element error relative to the largest reference element."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max()) / max(float(np.abs(b).max()), 1e-300)
+
+
 def _compare(case, g_gpu, d, u, v, phi_ref, tol=TOL):
     """Relative L2 of the state and of the velocity field (u, v) together;
-    rho - 1 relative to the state's norm."""
+    rho - 1 relative to the state's norm; and element by element, every
+    error within tol times the field's largest reference value (so a few
+    wrong wall or corner nodes are not diluted by the norm)."""
     dr, ur, vr = oracle.moments(case, phi_ref)
     eg = _rel(g_gpu, phi_ref)
     evel = _rel(np.stack([u, v]), np.stack([ur, vr]))
     ed = float(np.linalg.norm(d - dr)) / float(np.linalg.norm(phi_ref))
-    print(f"    rel L2: g {eg:.3e}  (u,v) {evel:.3e}  rho-1 (vs ||g||) {ed:.3e}", flush=True)
+    mg = _max_rel(g_gpu, phi_ref)
+    mvel = _max_rel(np.stack([u, v]), np.stack([ur, vr]))
+    print(f"    rel L2: g {eg:.3e}  (u,v) {evel:.3e}  rho-1 (vs ||g||) {ed:.3e}; "
+          f"max-norm: g {mg:.3e}  (u,v) {mvel:.3e}", flush=True)
     assert eg <= tol and evel <= tol and ed <= tol
+    assert mg <= tol and mvel <= tol
     return eg, evel
 
 
@@ -170,6 +182,42 @@ def test_checkpoint_resume_bitwise():
     assert np.array_equal(g_full, g_resumed)
 
 
+@pytest.mark.parametrize("bound_side", [True, False])
+def test_side_stream_results_without_host_synchronisation(bound_side):
+    """The binding orders the bound stream against the caller's current
+    stream: with the context on a side stream and the caller on the default
+    one (or the reverse), inputs made on the caller's stream, 300 steps, a
+    checkpoint copy, more steps, a restore and the read-backs follow each
+    other with no host synchronisation; results used on the caller's stream
+    equal the oracle's state and moments."""
+    case = W.cavity_case(128, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
+    print(f"[gpu] side stream, bound_side={bound_side}", flush=True)
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 300)
+    d_ref, u_ref, v_ref = oracle.moments(case, ref)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    if bound_side:
+        ctx = t2s2.context_for_case(case, stream=side)
+        caller = torch.cuda.current_stream()
+    else:
+        ctx = t2s2.context_for_case(case, stream=torch.cuda.current_stream())
+        caller = side
+    with torch.cuda.stream(caller):
+        ctx.init_distributions(torch.from_numpy(phi0))
+        ctx.step(300)
+        saved = ctx.save_state()
+        ctx.step(200)
+        ctx.restore_state(saved)
+        g = ctx.read_distributions() * 1.0  # consumed on the caller's stream
+        d, u, v = ctx.moments()
+        gh, dh, uh, vh = g.cpu().numpy(), d.cpu().numpy(), u.cpu().numpy(), v.cpu().numpy()
+    assert _rel(gh, ref) < 1e-12
+    assert _rel(uh, u_ref) < 1e-12 and _rel(vh, v_ref) < 1e-12
+    assert np.abs(dh - d_ref).max() <= 1e-12 * np.abs(d_ref).max()
+    ctx.close()
+
+
 def test_init_macro_with_eq_3_5_matches_oracle():
     case = W.tgv_case(64, 48, k1=1.0, k2=2.0, u0=0.05, nu=0.01, cfl=0.5)
     ctx = t2s2.context_for_case(case)
@@ -183,10 +231,13 @@ def test_init_macro_with_eq_3_5_matches_oracle():
 
 
 def test_diagnostics_match_host_sums():
+    """t2s2_diagnostics against host sums over the oracle's state after the
+    same 100 steps (trapezoid measure of the separable mesh)."""
     case = W.cavity_case(64, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
     phi0 = oracle.init(case)
-    ctx, g, d, u, v = _gpu_run(case, phi0, 100)
+    ctx, g, _, _, _ = _gpu_run(case, phi0, 100)
     diag = ctx.diagnostics()
+    d, u, v = oracle.moments(case, oracle.run(case, phi0, 100))
     def trapezoid(c):
         J = np.empty_like(c)
         J[1:-1] = 0.5 * (c[2:] - c[:-2])
@@ -196,9 +247,10 @@ def test_diagnostics_match_host_sums():
 
     J = trapezoid(case.y)[:, None] * trapezoid(case.x)[None, :]
     rho = 1.0 + d
-    assert diag["mass_excess"] == pytest.approx(np.sum(J * d), rel=1e-12, abs=1e-20)
+    assert diag["mass_excess"] == pytest.approx(np.sum(J * d), rel=1e-10,
+                                                abs=1e-12 * np.sum(J * np.abs(d)))
     assert diag["kinetic_energy"] == pytest.approx(np.sum(J * rho * 0.5 * (u * u + v * v)), rel=1e-12)
-    assert diag["max_speed"] == pytest.approx(np.max(np.hypot(u, v)), rel=1e-14)
+    assert diag["max_speed"] == pytest.approx(np.max(np.hypot(u, v)), rel=1e-12)
     assert diag["nonfinite"] == 0
     # deterministic: a second call gives the same bits
     assert ctx.diagnostics() == diag
