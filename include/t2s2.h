@@ -183,6 +183,22 @@ int t2s2_read_distributions(t2s2_ctx* ctx, double* g);
  * out[3] > 0. */
 int t2s2_diagnostics(t2s2_ctx* ctx, double out[T2S2_NDIAG]);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops that allow no allocation and no host synchronisation): the values
+ * of t2s2_diagnostics for the current state, written to device memory
+ * out[T2S2_NDIAG] (FP64, 8-byte aligned) on the bound stream, asynchronous;
+ * bitwise those of t2s2_diagnostics (same kernels, same reduction order).
+ * The reduction partials live in a static device array of the library
+ * (kept per device until the process ends; 32 KiB, enough for the fixed
+ * partial grid of any mesh, so no mesh is refused for its size) instead of
+ * the workspace; no memory is allocated and no HIP call that allocates is
+ * made.  No error code for non-finite populations: out[3] counts them.
+ * Calls that overlap on one device (several streams or threads) share the
+ * array and race; every call overwrites all of the partials it reads.
+ * Errors: INVALID_ARG (NULL context, NULL or misaligned out), NOT_BOUND,
+ * UNSUPPORTED (device index >= 64), HIP_ERROR. */
+int t2s2_diagnostics_noalloc(t2s2_ctx* ctx, double* out);
+
 /* Global relative error of the velocity (eq 3.6) against a reference field
  * u' = (ux_ref, uy_ref): device FP64 arrays [ny][nx] (row-major, no pitch),
  * read only.  out (host, T2S2_NGRE doubles) receives, over all nodes of the

@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
         "t2s2_moments": (i, [vp, vp, vp, vp]),
         "t2s2_read_distributions": (i, [vp, vp]),
         "t2s2_diagnostics": (i, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "t2s2_diagnostics_noalloc": (i, [vp, vp]),
         "t2s2_velocity_error": (i, [vp, vp, vp, ctypes.POINTER(ctypes.c_double)]),
         "t2s2_stencil_weights": (i, [vp, vp, vp]),
         "t2s2_omega": (d, [vp]),
@@ -138,7 +139,7 @@ def exported_symbols() -> Sequence[str]:
             "t2s2_init_macro", "t2s2_init_distributions", "t2s2_step", "t2s2_graph_capture",
             "t2s2_graph_step", "t2s2_current",
             "t2s2_steps_taken", "t2s2_dt", "t2s2_moments", "t2s2_read_distributions",
-            "t2s2_diagnostics", "t2s2_velocity_error", "t2s2_stencil_weights", "t2s2_omega", "t2s2_adjoint_state_bytes",
+            "t2s2_diagnostics", "t2s2_diagnostics_noalloc", "t2s2_velocity_error", "t2s2_stencil_weights", "t2s2_omega", "t2s2_adjoint_state_bytes",
             "t2s2_adjoint_scratch_bytes", "t2s2_bind_adjoint", "t2s2_adjoint_seed_velocity",
             "t2s2_adjoint_step", "t2s2_step_save_s", "t2s2_adjoint_step_stored",
             "t2s2_adjoint_init_macro", "t2s2_adjoint_read",
@@ -429,6 +430,18 @@ class Context:
         lam = self.adjoint_buffer()
         self._call(_lib.t2s2_adjoint_load, d.data_ptr(), lam.data_ptr(), tensors=(d, lam))
         return lam
+
+    def diagnostics_noalloc(self, out=None):
+        """t2s2_diagnostics_noalloc: the diagnostics of the current state into
+        a device FP64 tensor of NDIAG values (allocated here when out is None;
+        the library allocates nothing), asynchronous."""
+        t = self._torch
+        if out is None:
+            out = t.empty(NDIAG, dtype=t.float64, device=self.device)
+        if out.dtype != t.float64 or out.numel() < NDIAG or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float64 tensor of >= {NDIAG} values")
+        self._call(_lib.t2s2_diagnostics_noalloc, out.data_ptr(), tensors=(out,))
+        return out
 
     def diagnostics(self, raise_nonfinite: bool = True) -> dict:
         out = (ctypes.c_double * NDIAG)()

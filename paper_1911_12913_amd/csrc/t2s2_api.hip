@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -156,8 +157,37 @@ int plan_blocks(StepParams& p, int storage, int cus) {
 
 }  // namespace
 
+// Reduction partials of t2s2_diagnostics_noalloc: a file-scope device array
+// (one copy per device, held until the process ends) instead of workspace
+// memory.  In host code `scratch` names a host-side stand-in, not device
+// memory; its device address comes from hipGetSymbolAddress, once per device
+// (scratch_address), and only that address reaches the kernels.
+constexpr int kNoAllocDoubles = kDiagBlocks * kDiagSlots;  // 32 KiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current; looked
+// up on the first call for that device and kept.
+hipError_t scratch_address(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 struct t2s2_ctx {
   t2s2_config cfg;
+  int device = -1;  // device current at bind
   int nx = 0, ny = 0;
   long long pitch = 0;
   double dt = 0, tau = 0, omega = 0;
@@ -439,6 +469,7 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e, "bind: device query");
+  c->device = dev;
   c->grid = plan_blocks(c->sp, c->cfg.storage, cus);
   c->grid_gen = c->sp.single ? plan_blocks(c->sp_gen, c->cfg.storage, cus) : c->grid;
   // Small meshes take the tile kernel (scheme 1, A > 0), when a march would
@@ -592,7 +623,8 @@ int t2s2_diagnostics(t2s2_ctx* c, double out[T2S2_NDIAG]) {
   if (!out) return fail(T2S2_ERR_INVALID_ARG, "NULL output");
   double* part = reinterpret_cast<double*>(c->ws + c->off_part);
   double* res = reinterpret_cast<double*>(c->ws + c->off_res);
-  hipError_t e = launch_diagnostics(c->cfg.storage, c->ap, c->state[c->cur], part, res, c->stream);
+  hipError_t e = launch_diagnostics(c->cfg.storage, c->ap, c->state[c->cur], part, res,
+                                    kDiagSlots, c->stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostics");
   double host[kDiagSlots];
   e = hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, c->stream);
@@ -601,6 +633,32 @@ int t2s2_diagnostics(t2s2_ctx* c, double out[T2S2_NDIAG]) {
   if (e != hipSuccess) return hip_fail(e, "diagnostics: synchronize");
   for (int k = 0; k < T2S2_NDIAG; ++k) out[k] = host[k];
   if (host[3] > 0.0) return fail(T2S2_ERR_NONFINITE, "non-finite populations in the state");
+  return T2S2_OK;
+}
+
+int t2s2_diagnostics_noalloc(t2s2_ctx* c, double* out) {
+  g_last_error.clear();
+  if (!c) return fail(T2S2_ERR_INVALID_ARG, "NULL context");
+  if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
+  if (!out || (reinterpret_cast<uintptr_t>(out) & 7))
+    return fail(T2S2_ERR_INVALID_ARG, "out must be an 8-byte aligned device pointer");
+  // The partials take kDiagBlocks * kDiagSlots doubles for any mesh (a
+  // fixed grid of partial blocks), which the array holds.
+  static_assert(kDiagBlocks * kDiagSlots <= kNoAllocDoubles, "scratch too small");
+  if (c->device < 0 || c->device >= kMaxDevices)
+    return fail(T2S2_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics_noalloc: device query");
+  if (cur != c->device && (e = hipSetDevice(c->device)) != hipSuccess)
+    return hip_fail(e, "diagnostics_noalloc: set device");
+  double* part = nullptr;
+  e = scratch_address(c->device, &part);
+  if (e == hipSuccess)
+    e = launch_diagnostics(c->cfg.storage, c->ap, c->state[c->cur], part, out, T2S2_NDIAG,
+                           c->stream);
+  if (cur != c->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics_noalloc");
   return T2S2_OK;
 }
 

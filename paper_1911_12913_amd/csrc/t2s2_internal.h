@@ -169,8 +169,10 @@ hipError_t launch_read_dist(int storage, const AuxParams& a, const void* state, 
                             hipStream_t s);
 hipError_t launch_moments(int storage, const AuxParams& a, const void* state, double* drho,
                           double* ux, double* uy, hipStream_t s);
+// kDiagBlocks * kDiagSlots partials; the first nout of the kDiagSlots
+// results go to result.
 hipError_t launch_diagnostics(int storage, const AuxParams& a, const void* state,
-                              double* partials, double* result, hipStream_t s);
+                              double* partials, double* result, int nout, hipStream_t s);
 hipError_t launch_velocity_error(int storage, const AuxParams& a, const void* state,
                                  const double* uref, const double* vref, double* partials,
                                  double* result, hipStream_t s);

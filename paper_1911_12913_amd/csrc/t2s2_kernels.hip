@@ -1206,8 +1206,9 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(AuxParams a, const St
 // lanes.  The loads of a lane are independent, so they are in flight
 // together (a walk over the blocks one at a time waited out a cache round
 // trip per block).
+// The first nout slots go to result.
 __global__ __launch_bounds__(256) void diag_final_kernel(const double* partials, int nblocks,
-                                                         double* result) {
+                                                         double* result, int nout) {
   const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
   for (int k = wave; k < kDiagSlots; k += 256 / kLanes) {  // uniform per wave
     double acc = 0.0;
@@ -1216,7 +1217,7 @@ __global__ __launch_bounds__(256) void diag_final_kernel(const double* partials,
       acc = (k == 2) ? fmax(acc, v) : acc + v;
     }
     acc = k == 2 ? wave_max(acc) : wave_sum(acc);
-    if (lane == 0) result[k] = acc;
+    if (lane == 0 && k < nout) result[k] = acc;
   }
 }
 
@@ -1471,13 +1472,14 @@ hipError_t launch_moments(int storage, const AuxParams& a, const void* state, do
 }
 
 hipError_t launch_diagnostics(int storage, const AuxParams& a, const void* state,
-                              double* partials, double* result, hipStream_t s) {
+                              double* partials, double* result, int nout, hipStream_t s) {
   T2S2_DISPATCH(storage,
                 hipLaunchKernelGGL(diag_partial_kernel<Store>, dim3(kDiagBlocks), dim3(256), 0,
                                    s, a, static_cast<const Store*>(state), partials));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partials, kDiagBlocks, result);
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partials, kDiagBlocks, result,
+                     nout);
   return hipGetLastError();
 }
 
@@ -1489,7 +1491,8 @@ hipError_t launch_velocity_error(int storage, const AuxParams& a, const void* st
                                    s, a, static_cast<const Store*>(state), uref, vref, partials));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partials, kDiagBlocks, result);
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partials, kDiagBlocks, result,
+                     kDiagSlots);
   return hipGetLastError();
 }
 

@@ -126,6 +126,8 @@ def test_calls_on_unbound_context_fail_without_device():
     out = (ctypes.c_double * t2s2.NGRE)()
     assert lib.t2s2_velocity_error(h, None, None, out) == t2s2.ERR_NOT_BOUND
     assert lib.t2s2_velocity_error(None, None, None, out) == t2s2.ERR_INVALID_ARG
+    assert lib.t2s2_diagnostics_noalloc(h, None) == t2s2.ERR_NOT_BOUND
+    assert lib.t2s2_diagnostics_noalloc(None, None) == t2s2.ERR_INVALID_ARG
     assert lib.t2s2_step_save_s(h, None, None, None) == t2s2.ERR_NOT_BOUND
     assert lib.t2s2_step_save_s(None, None, None, None) == t2s2.ERR_INVALID_ARG
     assert lib.t2s2_adjoint_step_stored(h, None, None, None, None, None, None) == t2s2.ERR_NOT_BOUND
