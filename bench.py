@@ -44,7 +44,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-BYTES_PER_NODE = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36}
+BYTES_PER_NODE = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36, "bf16sr": 36, "f16sr": 36}
 METRIC = "D2Q9 MLUPS & % HBM peak, FP64 vs FP32/BF16-store at stated L2 error"
 KERNEL_SOURCES = ["paper_1911_12913_amd/csrc/t2s2_kernels.hip",
                   "paper_1911_12913_amd/csrc/t2s2_device.h",
@@ -384,7 +384,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=4096, help="grid side")
     ap.add_argument("--storage", default="f64", choices=sorted(BYTES_PER_NODE))
     ap.add_argument("--nu", type=float, default=1e-4)
-    ap.add_argument("--forms", default="f32,bf16,f16",
+    ap.add_argument("--forms", default="f32,bf16,f16,bf16sr,f16sr",
                     help="reduced-storage forms run after the headline one, each with the "
                          "same steps; their speed-up and velocity error are reported")
     ap.add_argument("--cpu-steps", type=int, default=8,

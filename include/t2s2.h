@@ -48,14 +48,25 @@ extern "C" {
 
 /* Storage of the carried state g = f~ - w.  T2S2_F64 computes in FP64; the
  * reduced forms compute in FP32 with FP64 moment sums.  The state buffers
- * hold g rounded to nearest even, except T2S2_F16_DEV, which holds
- * 2^14 g (an exact power-of-two scale, so deviations down to about 4e-9
- * stay normal FP16 numbers; |g| >= 4 overflows).  The calls that take or
- * return FP64 fields and distributions convert to and from g. */
+ * hold g rounded to nearest even, except the FP16 forms, which hold 2^14 g
+ * (an exact power-of-two scale, so deviations down to about 4e-9 stay
+ * normal FP16 numbers; |g| >= 4 overflows).  T2S2_BF16_SR_DEV and
+ * T2S2_F16_SR_DEV hold the bits of T2S2_BF16_DEV and T2S2_F16_DEV, but the
+ * step rounds the new interior values it stores stochastically (up in
+ * magnitude with probability equal to the fraction of the unit in the last
+ * place cut off; random bits from a hash of the node's position and new
+ * values, so results do not depend on the launch tiling and are
+ * reproducible): increments below half a unit in the last place, lost
+ * under rounding to nearest, are kept on average.  Initialisation and wall
+ * nodes round to nearest.  The stochastic forms run T2S2_FDLBM1 (any A)
+ * only, without the adjoint.  The calls that take or return FP64 fields and
+ * distributions convert to and from g. */
 #define T2S2_F64 0
 #define T2S2_F32_DEV 1
 #define T2S2_BF16_DEV 2
 #define T2S2_F16_DEV 3
+#define T2S2_BF16_SR_DEV 4
+#define T2S2_F16_SR_DEV 5
 
 /* Time-marching scheme (Sec. 2A, Sec. 2D).  T2S2_FDLBM1: eq 2.23, the
  * intermediate stage at t + A dt (A = 1/2: T2S2-FDLBM1, A = 0: T1S2).
@@ -87,7 +98,8 @@ typedef struct t2s2_config {
   int periodic_y;
   double period_x;
   double period_y;
-  int storage;          /* T2S2_F64, T2S2_F32_DEV, T2S2_BF16_DEV, T2S2_F16_DEV */
+  int storage;          /* T2S2_F64, T2S2_F32_DEV, T2S2_BF16_DEV, T2S2_F16_DEV,
+                           T2S2_BF16_SR_DEV, T2S2_F16_SR_DEV */
   int scheme;           /* T2S2_FDLBM1 (0 is read as this), T2S2_FDLBM2 or
                            T2S2_FAMILY */
   double btilde[3];     /* T2S2_FAMILY only: (B~0, B~1, B~2), each >= 0,

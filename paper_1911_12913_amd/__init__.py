@@ -17,8 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libt2s2.so")
 
 OK, ERR_INVALID_ARG, ERR_HIP, ERR_UNSUPPORTED, ERR_NONFINITE, ERR_NOT_BOUND = range(6)
-F64, F32_DEV, BF16_DEV, F16_DEV = range(4)
-STORAGE = {"f64": F64, "f32": F32_DEV, "bf16": BF16_DEV, "f16": F16_DEV}
+F64, F32_DEV, BF16_DEV, F16_DEV, BF16_SR_DEV, F16_SR_DEV = range(6)
+STORAGE = {"f64": F64, "f32": F32_DEV, "bf16": BF16_DEV, "f16": F16_DEV, "bf16sr": BF16_SR_DEV,
+           "f16sr": F16_SR_DEV}
 NDIAG = 6
 DIAG_NAMES = ("mass_excess", "kinetic_energy", "max_speed", "nonfinite", "momentum_x",
               "momentum_y")

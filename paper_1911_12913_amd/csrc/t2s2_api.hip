@@ -255,11 +255,14 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   if (cfg->dt > 0.0 && !std::isfinite(cfg->dt)) return fail(T2S2_ERR_INVALID_ARG, "dt not finite");
   if (!(cfg->eta >= 0.0 && cfg->eta <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "eta not in [0,1]");
   if (!(cfg->A >= 0.0 && cfg->A <= 1.0)) return fail(T2S2_ERR_INVALID_ARG, "A not in [0,1]");
-  if (cfg->storage < T2S2_F64 || cfg->storage > T2S2_F16_DEV)
+  if (cfg->storage < T2S2_F64 || cfg->storage > T2S2_F16_SR_DEV)
     return fail(T2S2_ERR_INVALID_ARG, "unknown storage");
   if (cfg->scheme != 0 && cfg->scheme != T2S2_FDLBM1 && cfg->scheme != T2S2_FDLBM2 &&
       cfg->scheme != T2S2_FAMILY)
     return fail(T2S2_ERR_INVALID_ARG, "unknown scheme");
+  if ((cfg->storage == T2S2_BF16_SR_DEV || cfg->storage == T2S2_F16_SR_DEV) &&
+      cfg->scheme != 0 && cfg->scheme != T2S2_FDLBM1)
+    return fail(T2S2_ERR_UNSUPPORTED, "stochastically rounded storage runs T2S2_FDLBM1 only");
   if (cfg->scheme == T2S2_FAMILY) {
     const double* b = cfg->btilde;
     for (int k = 0; k < 3; ++k)
@@ -715,6 +718,8 @@ int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
   if (!c->bound) return fail(T2S2_ERR_NOT_BOUND, "context not bound");
   if (c->sp.has_force) return fail(T2S2_ERR_UNSUPPORTED, "the adjoint covers unforced flows");
   if (c->sp.scheme != 1) return fail(T2S2_ERR_UNSUPPORTED, "the adjoint covers T2S2-FDLBM1 / T1S2");
+  if (c->cfg.storage == T2S2_BF16_SR_DEV || c->cfg.storage == T2S2_F16_SR_DEV)
+    return fail(T2S2_ERR_UNSUPPORTED, "the adjoint covers the storage forms rounded to nearest");
   if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255))
     return fail(T2S2_ERR_INVALID_ARG, "scratch must be a 256-byte aligned device pointer");
   AdjParams& a = c->adj;

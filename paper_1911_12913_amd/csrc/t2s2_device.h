@@ -63,12 +63,91 @@ struct Cvt<_Float16> {
   __device__ static _Float16 st(float v) { return static_cast<_Float16>(v * kF16Scale); }  // RNE
 };
 
+// The stochastically rounded 16-bit forms: the same bits as Bf16 and
+// _Float16 storage (FP16 with the 2^14 scale), read the same way; the new
+// interior values a step stores are rounded stochastically (round_node_sr
+// below), every other store (initialisation, wall nodes) to nearest even.
+struct Bf16Sr {
+  unsigned short bits;
+};
+struct F16Sr {
+  _Float16 v;
+};
+template <>
+struct Cvt<Bf16Sr> {
+  using R = float;
+  __device__ static float ld(Bf16Sr v) { return Cvt<Bf16>::ld(Bf16{v.bits}); }
+  __device__ static Bf16Sr st(float v) { return Bf16Sr{Cvt<Bf16>::st(v).bits}; }
+};
+template <>
+struct Cvt<F16Sr> {
+  using R = float;
+  __device__ static float ld(F16Sr v) { return Cvt<_Float16>::ld(v.v); }
+  __device__ static F16Sr st(float v) { return F16Sr{Cvt<_Float16>::st(v)}; }
+};
+template <typename S>
+constexpr bool kStochastic = std::is_same<S, Bf16Sr>::value || std::is_same<S, F16Sr>::value;
+// BF16 bits, either rounding.
+template <typename S>
+constexpr bool kBf16Bits = std::is_same<S, Bf16>::value || std::is_same<S, Bf16Sr>::value;
+
 // Storage code of a storage type.
 template <typename S>
-constexpr int kStorageOf = std::is_same<S, double>::value  ? kF64
-                           : std::is_same<S, float>::value ? kF32
-                           : std::is_same<S, Bf16>::value  ? kBF16
-                                                           : kF16;
+constexpr int kStorageOf = std::is_same<S, double>::value   ? kF64
+                           : std::is_same<S, float>::value  ? kF32
+                           : std::is_same<S, Bf16>::value   ? kBF16
+                           : std::is_same<S, _Float16>::value ? kF16
+                           : std::is_same<S, Bf16Sr>::value ? kBF16Sr
+                                                            : kF16Sr;
+
+// 32-bit integer mixing function (the "lowbias32" hash published by
+// C. Wellons): every output bit depends on every input bit.
+__device__ inline unsigned mix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Stochastic rounding of the nine new values v of one node to 16 bits:
+// value x rounds up in magnitude with probability (x - x_down) / (x_up -
+// x_down), so the stored value is x on average and increments smaller than
+// half a unit in the last place are kept on average instead of lost, as
+// they are under rounding to nearest.  The random bits come from a counter
+// generator that needs no step counter: mix32 of the node's position (pos) and of the nine values'
+// FP32 bits, then a linear congruential sequence (multiplier 1664525,
+// increment 1013904223, on the low 24 bits of the state) whose upper 16
+// bits serve one value each.  They depend only on the node and the values,
+// so results do not depend on the launch's tiling, graph replays give the
+// values of plain launches, and a state that does not change rounds the
+// same way again.  BF16: add 16 random bits to the FP32 bits and cut them;
+// FP16: the same with 13 bits on 2^14 x, then an exact conversion (in the
+// normal FP16 range; below it, 2^14 |x| < 6.1e-5, the conversion rounds to
+// nearest).  Non-finite values keep their class (canonical NaNs, Inf).
+template <typename S>
+__device__ inline void round_node_sr(const float v[kQ], unsigned pos, S out[kQ]) {
+  constexpr bool kBf = std::is_same<S, Bf16Sr>::value;
+  unsigned b[kQ];
+  unsigned fold = pos;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    b[q] = __float_as_uint(kBf ? v[q] : v[q] * kF16Scale);
+    fold += b[q];
+  }
+  unsigned st = mix32(fold);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    st = __umul24(st, 1664525u) + 1013904223u;
+    if constexpr (kBf) {
+      out[q] = Bf16Sr{static_cast<unsigned short>((b[q] + (st >> 16)) >> 16)};
+    } else {
+      const float t = __uint_as_float((b[q] + (st >> 19)) & ~0x1FFFu);
+      out[q] = F16Sr{static_cast<_Float16>(t)};
+    }
+  }
+}
 
 // Value of the neighbouring lane l-1 (from_below) or l+1 (from_above) of a
 // wave64, through DPP wave shifts (two 32-bit moves for a double).  Every

@@ -39,8 +39,9 @@ constexpr int kRing = 8;
 constexpr int kTaps = 4;
 constexpr int kWeightsPerNode = 2 * kTaps;
 
-// Storage codes (match include/t2s2.h).
-enum Storage { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3 };
+// Storage codes (match include/t2s2.h).  kBF16Sr and kF16Sr hold the bits
+// of kBF16 and kF16; the step rounds its new interior values stochastically.
+enum Storage { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3, kBF16Sr = 4, kF16Sr = 5 };
 
 // Strips marched side by side by one block of the fused step.  Two for the
 // FP32-storage T2S2-FDLBM1 family: the cache lines the two strips share

@@ -71,6 +71,23 @@ __device__ inline T* at_byte(T* base, unsigned boff) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
 }
 
+// The nine new values of one interior node at byte offset boff of each
+// plane: rounded to nearest even, or, for the stochastic forms, by
+// round_node_sr with the node's offset as its position.
+template <typename Store>
+__device__ inline void store_node(Store* dst, long long plane, unsigned boff,
+                                  const typename Cvt<Store>::R (&out)[kQ]) {
+  if constexpr (kStochastic<Store>) {
+    Store r[kQ];
+    round_node_sr(out, boff, r);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) store_state(at_byte(dst + q * plane, boff), r[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) store_state(at_byte(dst + q * plane, boff), Cvt<Store>::st(out[q]));
+  }
+}
+
 // Row index brought into [0, n) by whole periods; the rows a piece touches
 // lie within a few rows of the grid, so this loops at most a few times.
 __device__ inline int wrap_near(int i, int n) {
@@ -198,7 +215,7 @@ constexpr int kMinWaves =
     sizeof(typename Cvt<Store>::R) == 8
         ? ((kScheme == 1 || (kScheme == 2 && !kWalls)) ? 2 : 1)
         : (kScheme == 3 ? 2
-                        : ((kScheme == 2 || kForce || std::is_same<Store, Bf16>::value ||
+                        : ((kScheme == 2 || kForce || kBf16Bits<Store> || kStochastic<Store> ||
                             (kWalls && !std::is_same<Store, float>::value))
                                ? 3
                                : 4));
@@ -594,9 +611,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
             const unsigned boff =
                 (static_cast<unsigned>(o) * static_cast<unsigned>(pitch) + static_cast<unsigned>(c)) *
                 static_cast<unsigned>(sizeof(Store));
-#pragma unroll
-            for (int q = 0; q < kQ; ++q)
-              store_state(at_byte(dst + q * plane, boff), Cvt<Store>::st(out[q]));
+            store_node(dst, plane, boff, out);
           }
         }
       }
@@ -833,9 +848,7 @@ __global__ __launch_bounds__(kTileWaves * kLanes) void tile_step_kernel(StepPara
         const unsigned boff =
             (static_cast<unsigned>(o) * static_cast<unsigned>(pitch) + static_cast<unsigned>(c)) *
             static_cast<unsigned>(sizeof(Store));
-#pragma unroll
-        for (int q = 0; q < kQ; ++q)
-          store_state(at_byte(dst + q * plane, boff), Cvt<Store>::st(out[q]));
+        store_node(dst, plane, boff, out);
       }
     }
   }
@@ -1054,9 +1067,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, 0), (kMinWaves<Stor
             const unsigned boff =
                 (static_cast<unsigned>(o) * static_cast<unsigned>(pitch) + static_cast<unsigned>(c)) *
                 static_cast<unsigned>(sizeof(Store));
-#pragma unroll
-            for (int q = 0; q < kQ; ++q)
-              store_state(at_byte(dst + q * plane, boff), Cvt<Store>::st(out[q]));
+            store_node(dst, plane, boff, out);
           }
         }
       }
@@ -1319,12 +1330,14 @@ hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
     launch_tile<Store>(p, s, walls);
   else if (p.single)
     launch_single<Store>(p, g, b, s, walls);
+  else if (p.scheme == 1)
+    launch_fused<Store, 1>(p, g, b, s, walls);
+  else if constexpr (kStochastic<Store>)
+    return hipErrorInvalidValue;  // the stochastic forms run scheme 1 only
   else if (p.scheme == 2)
     launch_fused<Store, 2>(p, g, b, s, walls);
-  else if (p.scheme == 3)
-    launch_fused<Store, 3>(p, g, b, s, walls);
   else
-    launch_fused<Store, 1>(p, g, b, s, walls);
+    launch_fused<Store, 3>(p, g, b, s, walls);
   return hipGetLastError();
 }
 
@@ -1343,6 +1356,8 @@ size_t storage_bytes(int storage) {
     case kF32: return 4;
     case kBF16: return 2;
     case kF16: return 2;
+    case kBF16Sr: return 2;
+    case kF16Sr: return 2;
     default: return 0;
   }
 }
@@ -1353,6 +1368,8 @@ size_t storage_bytes(int storage) {
     case kF32: { using Store = float; CALL; } break;                  \
     case kBF16: { using Store = Bf16; CALL; } break;                  \
     case kF16: { using Store = _Float16; CALL; } break;               \
+    case kBF16Sr: { using Store = Bf16Sr; CALL; } break;              \
+    case kF16Sr: { using Store = F16Sr; CALL; } break;                \
     default: return hipErrorInvalidValue;                             \
   }
 
@@ -1390,9 +1407,13 @@ int occupancy_single(bool force, bool walls) {
 template <typename Store>
 int occupancy_t(bool force, bool walls, int scheme) {
   if (scheme == 0) return occupancy_single<Store>(force, walls);
-  if (scheme == 2) return occupancy_s<Store, 2>(force, walls);
-  if (scheme == 3) return occupancy_s<Store, 3>(force, walls);
-  return occupancy_s<Store, 1>(force, walls);
+  if (scheme == 1) return occupancy_s<Store, 1>(force, walls);
+  if constexpr (kStochastic<Store>) {
+    return -1;  // scheme 1 only
+  } else {
+    if (scheme == 2) return occupancy_s<Store, 2>(force, walls);
+    return occupancy_s<Store, 3>(force, walls);
+  }
 }
 
 int step_blocks_per_cu(int storage, bool force, bool walls, int scheme) {
@@ -1401,6 +1422,8 @@ int step_blocks_per_cu(int storage, bool force, bool walls, int scheme) {
     case kF32: return occupancy_t<float>(force, walls, scheme);
     case kBF16: return occupancy_t<Bf16>(force, walls, scheme);
     case kF16: return occupancy_t<_Float16>(force, walls, scheme);
+    case kBF16Sr: return occupancy_t<Bf16Sr>(force, walls, scheme);
+    case kF16Sr: return occupancy_t<F16Sr>(force, walls, scheme);
     default: return -1;
   }
 }
@@ -1433,8 +1456,14 @@ hipError_t launch_step_save_s_t(const StepParams& p, int grid, hipStream_t s) {
 
 hipError_t launch_step_save_s(int storage, const StepParams& p, int grid, hipStream_t s) {
   if (p.has_force || p.scheme != 1 || p.single || !p.save_s) return hipErrorInvalidValue;
-  T2S2_DISPATCH(storage, return launch_step_save_s_t<Store>(p, grid, s));
-  return hipSuccess;
+  // The adjoint covers the storage forms rounded to nearest.
+  switch (storage) {
+    case kF64: return launch_step_save_s_t<double>(p, grid, s);
+    case kF32: return launch_step_save_s_t<float>(p, grid, s);
+    case kBF16: return launch_step_save_s_t<Bf16>(p, grid, s);
+    case kF16: return launch_step_save_s_t<_Float16>(p, grid, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_init_macro(int storage, const AuxParams& a, void* state, const double* rho,

@@ -306,7 +306,7 @@ def test_cavity2049_precision_forms_after_20000_steps():
     case = _cavity2049()
     ux0, uy0, rho0 = case.ux0, case.uy0, case.rho0
     vel, ms = {}, {}
-    for storage in ("f64", "f32", "f16", "bf16"):
+    for storage in ("f64", "f32", "f16", "bf16", "f16sr", "bf16sr"):
         _say(f"[gpu] cavity2049 storage={storage}: 20000 steps")
         ctx = t2s2.context_for_case(case, storage=storage)
         ctx.init_macro(rho0, ux0, uy0)
@@ -322,7 +322,9 @@ def test_cavity2049_precision_forms_after_20000_steps():
              f"nonfinite {diag['nonfinite']}")
         ctx.close()
         del ctx
-    bounds = {"f32": 1e-3, "f16": 0.5, "bf16": 1.0}
+    # rounding to nearest loses the small per-step increments (stagnation);
+    # stochastic rounding keeps them on average
+    bounds = {"f32": 1e-3, "f16": 0.5, "bf16": 1.0, "f16sr": 0.05, "bf16sr": 0.2}
     for storage, bound in bounds.items():
         e = _rel(vel[storage], vel["f64"])
         _say(f"    {storage}: velocity rel L2 vs FP64 after 20000 steps {e:.3e}")

@@ -318,6 +318,60 @@ def test_reduced_precision_error_vs_oracle(storage, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("storage,omega,steps", [("bf16", 1e-3, 400), ("f16", 1e-4, 1000)])
+def test_stochastic_rounding_keeps_sub_ulp_relaxation(storage, omega, steps):
+    """A spatially uniform non-equilibrium state at rest (zero mass and
+    momentum moments) relaxes as r^n with r = (2 - omega)/(2 + omega), the
+    Crank-Nicolson closed form (the oracle's pin).  With omega so small
+    that each step changes a value by less than half a unit in its last
+    place, the 16-bit form rounded to nearest stagnates; the stochastically
+    rounded one keeps the increments on average, so the domain mean follows
+    the closed form (advection conserves it on the periodic mesh)."""
+    n = 64
+    case = W.tgv_case(n, n, u0=0.0, nu=1.0, cfl=0.5, eta=0.1, noneq_init=False)
+    case.dt = omega * case.nu / oracle.CS2
+    a = 0.01
+    g0 = np.zeros((9, n, n))
+    g0[1] = g0[3] = a
+    g0[2] = g0[4] = -a
+    r = (2.0 - omega) / (2.0 + omega)
+    means = {}
+    for st in (storage, storage + "sr"):
+        _, g, *_ = _gpu_run(case, g0, steps, storage=st)
+        means[st] = float(np.mean(g[1])) / a
+    exact = r ** steps
+    print(f"    closed form {exact:.5f}; {storage} {means[storage]:.5f}; "
+          f"{storage}sr {means[storage + 'sr']:.5f}", flush=True)
+    assert abs(means[storage + "sr"] - exact) <= 0.01 * (1.0 - exact)
+    assert abs(means[storage] - exact) >= 0.5 * (1.0 - exact)  # stagnated
+
+
+@pytest.mark.parametrize("storage", ["bf16sr", "f16sr"])
+def test_stochastic_rounding_is_tiling_invariant_and_graph_exact(storage, monkeypatch):
+    """The random bits of the stochastic forms come from the node and its
+    values only: the state is bitwise the same for different block counts
+    and for graph replays against plain launches, on a walled cavity."""
+    case = W.cavity_case(96, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-4, seed=0)
+    phi0 = oracle.init(case)
+    outs = []
+    for blocks in ("8", "40"):
+        monkeypatch.setenv("T2S2_BLOCKS", blocks)
+        _, g, *_ = _gpu_run(case, phi0, 64, storage=storage)
+        outs.append(g)
+    monkeypatch.delenv("T2S2_BLOCKS")
+    s = torch.cuda.Stream()
+    ctx = t2s2.context_for_case(case, storage=storage, stream=s)
+    ctx.init_distributions(torch.from_numpy(phi0))
+    ctx.graph_capture(16)
+    ctx.graph_step(64)
+    outs.append(ctx.read_distributions().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    # the stochastic form differs from rounding to nearest, but not by much
+    _, g_rn, *_ = _gpu_run(case, phi0, 64, storage=storage[:-2])
+    assert not np.array_equal(outs[0], g_rn)
+    assert _rel(outs[0], g_rn) < 0.05
+
+
 # ------------------------------------------------------ T2S2-FDLBM2 (eq 5.23)
 
 def _ragged_cavity(cfl):
