@@ -29,6 +29,16 @@ def _dev(a):
     return torch.as_tensor(np.asarray(a), dtype=torch.float64, device="cuda:0")
 
 
+def _settle(fn, seconds=0.5):
+    """Run fn repeatedly for about `seconds` (the GPU clocks come up after
+    an idle or a host upload) before a timed run."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+
+
 def _one_walled_axis(walls_in_x):
     """Couette channel of 70 x 81 nodes (two strips across): walls on one axis only
     (tanh-stretched, one wall moving along it), the other axis periodic,
@@ -422,9 +432,7 @@ def test_adjoint_step_time_513(storage):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for label, fn in (("forward step", lambda: ctx.step(1)),
                       ("adjoint step", lambda: ctx.adjoint_step(state, lam_a, lam_b))):
-        for _ in range(5):
-            fn()
-        torch.cuda.synchronize()
+        _settle(fn)
         e0.record(ctx.stream)
         for _ in range(50):
             fn()
@@ -457,9 +465,7 @@ def test_adjoint_step_time_4096(storage):
     per_node = {"forward step": 18 * sb, "adjoint step": 9 * (3 * sb) + 9 * (4 * sb)}
     for label, fn in (("forward step", lambda: ctx.step(1)),
                       ("adjoint step", lambda: ctx.adjoint_step(state, lam_a, lam_b))):
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
+        _settle(fn)
         e0.record(ctx.stream)
         for _ in range(20):
             fn()
