@@ -360,7 +360,7 @@ def configs_leg(threads):
     c4 = W.cavity_case(2048, lid=0.1, re=5000.0, cfl=0.9, eta=0.05, noise=1e-6, seed=0)
     phi = oracle.init(c4)
     rec = {"gpu_steps": 200, "by_storage": {}}
-    for st in ("f64", "f32", "bf16", "f16"):
+    for st in ("f64", "f32", "bf16", "f16", "bf16sr", "f16sr"):
         gm, gms, _ = gpu_time(c4, st, 200, phi)
         rec["by_storage"][st] = {"gpu_mlups": gm, "gpu_us_per_step": gms * 1e3}
     om, osec, ref = oracle_time(c4, phi, 4, threads)

@@ -203,8 +203,8 @@ int t2s2_diagnostics(t2s2_ctx* ctx, double out[T2S2_NDIAG]);
  * The reduction partials live in a static device array of the library
  * (kept per device until the process ends; 32 KiB, enough for the fixed
  * partial grid of any mesh, so no mesh is refused for its size) instead of
- * the workspace; no memory is allocated and no HIP call that allocates is
- * made.  No error code for non-finite populations: out[3] counts them.
+ * the workspace; its device address is looked up by t2s2_bind.  No memory
+ * is allocated and no HIP call that allocates is made.  No error code for non-finite populations: out[3] counts them.
  * Calls that overlap on one device (several streams or threads) share the
  * array and race; every call overwrites all of the partials it reads.
  * Errors: INVALID_ARG (NULL context, NULL or misaligned out), NOT_BOUND,

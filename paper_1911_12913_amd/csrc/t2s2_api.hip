@@ -171,7 +171,7 @@ std::mutex g_scratch_mu;
 double* g_scratch_dev[kMaxDevices] = {};
 
 // Device address of `scratch` on device dev, which must be current; looked
-// up on the first call for that device and kept.
+// up on the first call for that device (t2s2_bind) and kept.
 hipError_t scratch_address(int dev, double** out) {
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   if (!g_scratch_dev[dev]) {
@@ -473,6 +473,14 @@ int t2s2_bind(t2s2_ctx* c, void* state_a, void* state_b, void* workspace, void* 
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e, "bind: device query");
   c->device = dev;
+  // The no-allocation diagnostics' scratch: its device address is looked up
+  // here, at set-up with the device current, so that the entry point itself
+  // (possibly under graph capture) makes no such call.
+  if (dev < kMaxDevices) {
+    double* scratch_dev = nullptr;
+    e = scratch_address(dev, &scratch_dev);
+    if (e != hipSuccess) return hip_fail(e, "bind: scratch address");
+  }
   c->grid = plan_blocks(c->sp, c->cfg.storage, cus);
   c->grid_gen = c->sp.single ? plan_blocks(c->sp_gen, c->cfg.storage, cus) : c->grid;
   // Small meshes take the tile kernel (scheme 1, A > 0), when a march would

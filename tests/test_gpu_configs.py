@@ -41,13 +41,18 @@ def _host_threads():
     return min(16, os.cpu_count() or 1)
 
 
-def _settle(ctx, seconds=0.5):
+def _settle(ctx, case, seconds=0.5):
     """Untimed steps for about `seconds` (the GPU clocks come up after the
-    host uploads of the initial fields) before a timed run."""
+    host uploads of the initial fields), then the initial state again from
+    fields already on the device (one short kernel, no idle GPU), so the
+    timed steps start from the initial state."""
+    fields = [torch.as_tensor(a, dtype=torch.float64, device="cuda:0").contiguous()
+              if a is not None else None for a in (case.rho0, case.ux0, case.uy0, case.grad0)]
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
         ctx.step(20)
         torch.cuda.synchronize()
+    ctx.init_macro(*fields)
 
 
 def _vel(ctx):
@@ -123,7 +128,7 @@ def test_tgv4096_scheme_throughput(storage, monkeypatch):
     for scheme, kw in ((1, {}), (2, {}), (3, dict(btilde=(0.25, 0.5, 0.25)))):
         ctx = t2s2.context_for_case(case, storage=storage, scheme=scheme, **kw)
         ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
-        _settle(ctx)
+        _settle(ctx, case)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(ctx.stream)
         ctx.step(100)
@@ -152,7 +157,7 @@ def test_tgv4096_t1s2_vs_t2s2_step_time(storage, monkeypatch):
     for A in (0.0, 0.5):
         ctx = t2s2.context_for_case(case, storage=storage, A=A)
         ctx.init_macro(case.rho0, case.ux0, case.uy0, case.grad0)
-        _settle(ctx)
+        _settle(ctx, case)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(ctx.stream)
         ctx.step(100)
@@ -310,8 +315,10 @@ def test_cavity2049_fp64_matches_oracle():
 def test_cavity2049_precision_forms_after_20000_steps():
     """Precision form on the 2049^2 cavity, 20000 steps: relative L2 of the
     velocity field of each storage form against the FP64 result (which
-    matches the oracle to round-off, see the test above).  Reported; the
-    bounds only catch a broken form."""
+    matches the oracle to round-off, see the test above).  The 16-bit forms
+    rounded to nearest stagnate (0.34 and 0.71, bounds that only catch a
+    broken form); the stochastically rounded ones (5e-4 and 4e-3 measured)
+    are held to ten times that."""
     case = _cavity2049()
     ux0, uy0, rho0 = case.ux0, case.uy0, case.rho0
     vel, ms = {}, {}
@@ -333,7 +340,7 @@ def test_cavity2049_precision_forms_after_20000_steps():
         del ctx
     # rounding to nearest loses the small per-step increments (stagnation);
     # stochastic rounding keeps them on average
-    bounds = {"f32": 1e-3, "f16": 0.5, "bf16": 1.0, "f16sr": 0.05, "bf16sr": 0.2}
+    bounds = {"f32": 1e-3, "f16": 0.5, "bf16": 1.0, "f16sr": 5e-3, "bf16sr": 3e-2}
     for storage, bound in bounds.items():
         e = _rel(vel[storage], vel["f64"])
         _say(f"    {storage}: velocity rel L2 vs FP64 after 20000 steps {e:.3e}")

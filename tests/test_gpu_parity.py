@@ -302,7 +302,8 @@ def test_velocity_error_eq36_and_residual():
     assert r["residual"] == pytest.approx(res, rel=1e-10)
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 3e-5), ("f16", 5e-2), ("bf16", 0.6)])
+@pytest.mark.parametrize("storage,tol", [("f32", 3e-5), ("f16", 5e-2), ("bf16", 0.6),
+                                         ("f16sr", 5e-2), ("bf16sr", 0.6)])
 def test_reduced_precision_error_vs_oracle(storage, tol):
     """Deviation storage in FP32 / FP16 / BF16 with FP32 arithmetic and FP64
     moment sums: velocity error against the FP64 oracle, reported and bounded.

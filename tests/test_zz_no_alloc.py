@@ -56,3 +56,35 @@ def test_diagnostics_noalloc_argument_checks():
     assert lib.t2s2_diagnostics_noalloc(ctx._h, ctypes.c_void_p(out.data_ptr() + 4)) == \
         t2s2.ERR_INVALID_ARG
     ctx.close()
+
+
+def test_diagnostics_noalloc_under_graph_capture():
+    """The no-allocation variant can be recorded into a HIP graph between
+    captured steps (no allocation, no host synchronisation): every replay
+    writes the diagnostics of the state it has just stepped to, bitwise those
+    of t2s2_diagnostics at the same point."""
+    lib = t2s2.load_library()
+    case = W.cavity_case(64, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-3, seed=4)
+    s = torch.cuda.Stream()
+    ctx = t2s2.context_for_case(case, stream=s)
+    ctx.init_distributions(torch.from_numpy(oracle.init(case)))
+    out = torch.zeros(t2s2.NDIAG, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        # two steps on the bound stream (the state returns to its buffer), then the diagnostics
+        assert lib.t2s2_step(ctx._h, 2) == t2s2.OK
+        assert lib.t2s2_diagnostics_noalloc(ctx._h, ctypes.c_void_p(out.data_ptr())) == t2s2.OK
+    torch.cuda.synchronize()
+    ref = t2s2.context_for_case(case)
+    ref.init_distributions(torch.from_numpy(oracle.init(case)))
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        ref.step(2)
+        want = np.array([ref.diagnostics()[k] for k in t2s2.DIAG_NAMES])
+        got = out.cpu().numpy()
+        print(f"    replay {rep}: {got[:3]}", flush=True)
+        assert np.array_equal(got, want), rep
+    ctx.close()
+    ref.close()
