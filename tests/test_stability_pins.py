@@ -129,6 +129,25 @@ def test_exact_model_predicts_the_tgv_cfl_09_finding():
     assert _full_k_max("fdlbm1", 4.6, 0.9, 17, **kw) <= 1.0 + 1e-12
 
 
+def test_fdlbm2_unstable_where_fdlbm1_is_stable_at_cfl_09():
+    """At the 4096^2 throughput setting (r = 0.9, eta = 0.01, dt/tau = 4.6)
+    the exact growth matrix of the eq 5.23 step has a growing mode and the
+    FDLBM1 one has none; the oracle agrees on a 64^2 Taylor-Green grid with
+    the same r and dt/tau: T2S2-FDLBM2 blows up within 1500 steps, FDLBM1
+    decays."""
+    kw = dict(eta=0.01, u=(0.01, 0.01))
+    assert _full_k_max("fdlbm2", 4.6, 0.9, 17, **kw) > 1.0 + 1e-3
+    assert _full_k_max("fdlbm1", 4.6, 0.9, 17, A=0.5, **kw) <= 1.0 + 1e-12
+    n = 64
+    case = W.tgv_case(n, n, u0=0.01, nu=1.0, cfl=0.9, eta=0.01)
+    case.nu = oracle.time_step(case) / 4.6 * CS2
+    phi0 = oracle.init(case) + W.random_state((9, n, n), 1e-9, 3)
+    a = oracle.run(case, phi0, 1500, scheme=1)
+    b = oracle.run(case, phi0, 1500, scheme=2)
+    assert np.isfinite(a).all() and np.abs(a).max() < np.abs(phi0).max()
+    assert not (np.isfinite(b).all() and np.abs(b).max() < 1.0)
+
+
 def test_largest_stable_region_is_the_crank_nicolson_member():
     """Sec. 2C: among the Fig. 1 settings, B-2 = 1/2, B~2 = 1/2, eta = 0.1
     gives the largest stable region in the (r, omega) plane (u = (0.2, 0.2),
