@@ -47,7 +47,8 @@ def _load():
         d, i, l, p = ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_void_p
         lib.oracle_run.argtypes = [i, i, p, p, i, i, d, d, d, d, d, d, d, d, p, d, i, p, l]
         lib.oracle_run.restype = i
-        lib.oracle_run_family.argtypes = [i, i, p, p, i, i, d, d, d, d, d, d, d, d, p, d, p, p, l]
+        lib.oracle_run_family.argtypes = [i, i, p, p, i, i, d, d, d, d, d, d, d, d, p, d, p, p, p,
+                                          l]
         lib.oracle_run_family.restype = i
         lib.oracle_init.argtypes = [i, i, p, p, p, p, d, d, d, p]
         lib.oracle_init.restype = i
@@ -124,12 +125,16 @@ def init(case, offset: float = 1.0, noneq: bool = True) -> np.ndarray:
 
 def run(case, phi: np.ndarray, nsteps: int, *, offset: float = 1.0, scheme: int = 1,
         A: float | None = None, eta: float | None = None, dt: float | None = None,
-        threads: int | None = None, btilde=None) -> np.ndarray:
+        threads: int | None = None, btilde=None, bbar=None) -> np.ndarray:
     """Advance a copy of phi by nsteps; returns the new state.
 
     scheme 1: T2S2-FDLBM1 family with h = A dt (A = 0.5 default, A = 0 is
     Guo's T1S2); scheme 2: T2S2-FDLBM2; scheme 3: the eq 2.13 family with
-    gradient weights btilde = (B~0, B~1, B~2) on L(f^n), L(f*), L(f^{n+1})."""
+    gradient weights btilde = (B~0, B~1, B~2) on L(f^n), L(f*), L(f^{n+1})
+    and collision weights bbar = (B-0, B-1, B-2) on Omega(f^n), Omega(f*),
+    Omega(f^{n+1}) (None: (1/2, 0, 1/2) in the explicit form of eqs
+    2.19-2.20; a given bbar always takes the node-by-node solve of the
+    implicit weight, also at (1/2, 0, 1/2))."""
     lib = _load()
     if threads is None:
         # small grids: thread start-up costs more than the stage loops
@@ -147,7 +152,9 @@ def run(case, phi: np.ndarray, nsteps: int, *, offset: float = 1.0, scheme: int 
             float(case.force[0]), float(case.force[1]), _ptr(uw), float(offset))
     if scheme == 3:
         bt = np.ascontiguousarray(btilde, dtype=np.float64).reshape(3)
-        rc = lib.oracle_run_family(*args, _ptr(bt), _ptr(out), int(nsteps))
+        bb = None if bbar is None else np.ascontiguousarray(bbar, dtype=np.float64).reshape(3)
+        rc = lib.oracle_run_family(*args, _ptr(bt), _ptr(bb) if bb is not None else None,
+                                   _ptr(out), int(nsteps))
     else:
         rc = lib.oracle_run(*args, int(scheme), _ptr(out), int(nsteps))
     if rc != 0:

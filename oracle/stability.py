@@ -11,12 +11,15 @@ equilibrium f^eq(rho = 1, u) (eq 4.4) is built two ways:
   the mixed difference;
 * ``fdlbm1`` / ``fdlbm2`` / ``family``: the exact linearisation of the
   implemented steps (the eq 2.23 march with h = A dt, the eq 5.23 march, and
-  the eq 2.13 family with gradient weights B~), composed from the Jacobians
-  of the pointwise maps and the difference symbol:
+  the eq 2.13 family with gradient weights B~ and collision weights B-),
+  composed from the Jacobians of the pointwise maps and the difference
+  symbol:
       fdlbm1:  G = J_Q - rS J_R (I - A rS) J_P
       fdlbm2:  G = J_Q - (rS / 2) [J_f + J_R1 (I - rS) J_Q]
       family:  G = J_Q - rS [B~0 J_f + B~1 J_R (I - A rS) J_P + B~2 J_R1 (I - rS) J_Q]
-  with J_X = c_Xg I + c_Xe Gamma (the coefficients of the P, Q, R maps).
+  with J_X = c_Xg I + c_Xe Gamma (the coefficients of the P, Q, R maps);
+  the family with B- other than (1/2, 0, 1/2) adds the explicit collision
+  terms and solves the implicit one (growth_family).
 
 Readings (listed in the design notes):
 * eq 4.8 is printed with the imaginary unit missing from two exponentials;
@@ -111,10 +114,16 @@ def growth_fdlbm2(theta_x, theta_y, omega, r, eta, u):
     return JQ - 0.5 * rS @ (Jf + JR @ (I - rS) @ JQ)
 
 
-def growth_family(theta_x, theta_y, omega, r, A, btilde, eta, u):
-    """Exact linearisation of the eq 2.13 family step with Bbar = (1/2, 0,
-    1/2) and gradient weights btilde on L(f^n), L(f*), L(f^{n+1}):
-        G = J_Q - rS [B~0 J_f + B~1 J_R(A) (I - A rS) J_P + B~2 J_R(1) (I - rS) J_Q]."""
+def growth_family(theta_x, theta_y, omega, r, A, btilde, eta, u, bbar=None):
+    """Exact linearisation of the eq 2.13 family step with gradient weights
+    btilde on L(f^n), L(f*), L(f^{n+1}).  With the collision weights of
+    eqs 2.21 and 5.21 (bbar None):
+        G = J_Q - rS [B~0 J_f + B~1 J_R(A) (I - A rS) J_P + B~2 J_R(1) (I - rS) J_Q].
+    With collision weights bbar = (B-0, B-1, B-2), the right side of eq 2.13
+    (dt Omega = w (Gamma - I) f, unforced)
+        Y = J_f + w (Gamma - I) [B-0 J_f + B-1 J_R(A) (I - A rS) J_P] - rS [...]
+    is solved for f^{n+1} from [(1 + B-2 w) I - B-2 w Gamma] f^{n+1} = Y, and
+    the state is f~ = [(1 + w/2) I - (w/2) Gamma] f^{n+1} (eq 2.19)."""
     I = np.eye(9)
     G = gamma(u)
     c, c0, c1 = coefficients(A, omega), coefficients(0.0, omega), coefficients(1.0, omega)
@@ -125,11 +134,19 @@ def growth_family(theta_x, theta_y, omega, r, A, btilde, eta, u):
     JR1 = c1["cRs"] * I + c1["cRe"] * G
     rS = r * np.diag(symbol(theta_x, theta_y, eta))
     b0, b1, b2 = btilde
-    return JQ - rS @ (b0 * Jf + b1 * JR @ (I - A * rS) @ JP + b2 * JR1 @ (I - rS) @ JQ)
+    Jstar = JR @ (I - A * rS) @ JP
+    grad = rS @ (b0 * Jf + b1 * Jstar + b2 * JR1 @ (I - rS) @ JQ)
+    if bbar is None:
+        return JQ - grad
+    c0b, c1b, c2b = bbar
+    w = omega
+    Y = Jf + w * (G - I) @ (c0b * Jf + c1b * Jstar) - grad
+    f_next = np.linalg.solve((1 + c2b * w) * I - c2b * w * G, Y)
+    return ((1 + w / 2) * I - (w / 2) * G) @ f_next
 
 
 def growth(model, theta_x, theta_y, omega, r, *, eta, u, A=0.5, B2bar=0.5, B2tilde=0.0,
-           btilde=(0.0, 1.0, 0.0)):
+           btilde=(0.0, 1.0, 0.0), bbar=None):
     if model == "paper":
         return growth_paper(theta_x, theta_y, omega, r, B2bar, B2tilde, eta, u)
     if model == "fdlbm1":
@@ -137,7 +154,7 @@ def growth(model, theta_x, theta_y, omega, r, *, eta, u, A=0.5, B2bar=0.5, B2til
     if model == "fdlbm2":
         return growth_fdlbm2(theta_x, theta_y, omega, r, eta, u)
     if model == "family":
-        return growth_family(theta_x, theta_y, omega, r, A, btilde, eta, u)
+        return growth_family(theta_x, theta_y, omega, r, A, btilde, eta, u, bbar)
     raise ValueError(model)
 
 

@@ -23,7 +23,8 @@
  * Guo's force term of eq 3.12 and the mixed central / second-order upwind
  * difference of eqs 2.36-2.38.  Wall nodes use non-equilibrium extrapolation
  * (eq 3.10).  The T2S2-FDLBM2 sequence (eq 5.23, Sec. 2D) is scheme 2; the
- * eq 2.13 family with general gradient weights B~ is step_family.
+ * eq 2.13 family with general gradient weights B~ and collision weights B-
+ * is step_family.
  *
  * Readings where the paper is silent or garbled (each one is listed with its
  * justification in the design notes of the repository):
@@ -347,16 +348,70 @@ static void step_fdlbm2(const grid_t* g, double* ft, double* Fn, double* Qp, dou
   nee_walls(g, out, dt / 2.0);
 }
 
-/* The eq 2.13 family with the collision weights of eqs 2.21 and 5.21,
- * Bbar = (1/2, 0, 1/2), and gradient weights bt = (B~0, B~1, B~2):
- *   f~^{n+1} = f~^{+,n} + dt [B~0 L(f^n) + B~1 L(f*) + B~2 L(f^{n+1})]
- * (eq 2.13 under the transform of eqs 2.19-2.20).  Each argument of L is
- * the paper's own prediction of it: f* by step (1) of the T2S2-FDLBM1
- * sequence (h = A dt), f^{n+1} by step (2) of the T2S2-FDLBM2 sequence
- * (h = dt), f^n by eq 2.52 at h = 0 (step (1) of the second sequence).
- * bt = (0, 1, 0) is eq 2.23, (1/2, 0, 1/2) eq 5.23 and (1, 0, 0) eq 2.18. */
-static void step_family(const grid_t* g, const double bt[3], double* ft, double* P, double* Fn,
-                        double* Qp, double* S, double* R1, double* R2) {
+/* Collision term of eq 2.4 with the force of eq 3.12,
+ *   Omega_bar(f) = -(f - f^eq) / tau + F,
+ * of an array of physical f at every node; f^eq and F from f's own moments
+ * (a physical f carries its whole momentum: no force shift). */
+static void collision_all(const grid_t* g, const double* a, double* om) {
+  const double it = g->inv_tau;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < g->ny; ++j)
+    for (int i = 0; i < g->nx; ++i) {
+      double d, rho, ux, uy;
+      moments(g, a, i, j, 0.0, &d, &rho, &ux, &uy);
+      for (int q = 0; q < Q; ++q) {
+        double feq = feq_minus_offset(q, d, rho, ux, uy);
+        double Fq = force_term(q, rho, ux, uy, feq + g->offset * W[q], g);
+        om[IDX(g, q, i, j)] = -(a[IDX(g, q, i, j)] - feq) * it + Fq;
+      }
+    }
+}
+
+/* The implicit collision weight B-2 of eq 2.13, solved node by node.  On
+ * entry y holds Y = f^{n+1} - b2 dt Omega_bar(f^{n+1}) at the interior nodes.
+ * Omega_bar conserves mass and adds rho F to the momentum, so f^{n+1} has
+ * the density of Y and the velocity  u = sum xi Y / rho + b2 dt F; with f^eq
+ * and F at (rho, u),
+ *   f^{n+1} = [Y + b2 dt (f^eq / tau + F)] / (1 + b2 dt / tau).
+ * On exit y holds the state f~^{n+1} = f^{n+1} - (dt/2) Omega_bar(f^{n+1})
+ * of eq 2.19 there. */
+static void implicit_collision_interior(const grid_t* g, double b2, double* y) {
+  const double dt = g->dt, it = g->inv_tau;
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < g->ny; ++j)
+    for (int i = 0; i < g->nx; ++i) {
+      if (is_wall(g, i, j)) continue;
+      double d, rho, ux, uy;
+      moments(g, y, i, j, b2 * dt, &d, &rho, &ux, &uy);
+      for (int q = 0; q < Q; ++q) {
+        double feq = feq_minus_offset(q, d, rho, ux, uy);
+        double Fq = force_term(q, rho, ux, uy, feq + g->offset * W[q], g);
+        double f = (y[IDX(g, q, i, j)] + b2 * dt * (feq * it + Fq)) / (1.0 + b2 * dt * it);
+        double omega_bar = -(f - feq) * it + Fq;
+        y[IDX(g, q, i, j)] = f - (dt / 2.0) * omega_bar;
+      }
+    }
+}
+
+/* The eq 2.13 family with gradient weights bt = (B~0, B~1, B~2) and
+ * collision weights bb = (B-0, B-1, B-2):
+ *   f^{n+1} - B-2 dt Omega_bar(f^{n+1})
+ *     = f^n + dt [B-0 Omega_bar(f^n) + B-1 Omega_bar(f*)]
+ *       + dt [B~0 L(f^n) + B~1 L(f*) + B~2 L(f^{n+1})].
+ * Each argument on the right is the paper's own prediction of it: f* by
+ * step (1) of the T2S2-FDLBM1 sequence (h = A dt), f^{n+1} by step (2) of
+ * the T2S2-FDLBM2 sequence (h = dt), f^n by eq 2.52 at h = 0 (step (1) of
+ * the second sequence).  The left side is solved node by node
+ * (implicit_collision_interior) and the state stays f~ = f - (dt/2)
+ * Omega_bar (eq 2.19).
+ * bb = NULL takes the collision weights of eqs 2.21 and 5.21,
+ * (1/2, 0, 1/2), in the explicit form of eqs 2.19-2.20 that they allow:
+ *   f~^{n+1} = f~^{+,n} + dt [B~0 L(f^n) + B~1 L(f*) + B~2 L(f^{n+1})];
+ * bt = (0, 1, 0) is then eq 2.23, (1/2, 0, 1/2) eq 5.23 and (1, 0, 0)
+ * eq 2.18.  Om0 and Om1 are used only with bb. */
+static void step_family(const grid_t* g, const double bt[3], const double* bb, double* ft,
+                        double* P, double* Fn, double* Qp, double* S, double* R1, double* R2,
+                        double* Om0, double* Om1) {
   const double h = g->A * g->dt, dt = g->dt;
   size_t n = (size_t)Q * g->nx * g->ny;
   collide_all(g, ft, h, P, Qp);      /* P = fbar^{+,h}(t_n), Qp = f~^{+,n} */
@@ -373,17 +428,26 @@ static void step_family(const grid_t* g, const double bt[3], double* ft, double*
   memcpy(R2, S, n * sizeof(double));
   unshift_interior(g, S, dt, R2);
   nee_walls(g, R2, 0.0);
+  if (bb) {
+    collision_all(g, Fn, Om0); /* Omega_bar(f^n) */
+    collision_all(g, R1, Om1); /* Omega_bar(f*) */
+  }
   memcpy(ft, Qp, n * sizeof(double));
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < g->ny; ++j)
     for (int i = 0; i < g->nx; ++i) {
       if (is_wall(g, i, j)) continue;
       for (int q = 0; q < Q; ++q) {
+        size_t k = IDX(g, q, i, j);
         double l = bt[0] * L_term(g, Fn, q, i, j) + bt[1] * L_term(g, R1, q, i, j) +
                    bt[2] * L_term(g, R2, q, i, j);
-        ft[IDX(g, q, i, j)] = Qp[IDX(g, q, i, j)] + dt * l;
+        if (bb)
+          ft[k] = Fn[k] + dt * (bb[0] * Om0[k] + bb[1] * Om1[k]) + dt * l;
+        else
+          ft[k] = Qp[k] + dt * l;
       }
     }
+  if (bb) implicit_collision_interior(g, bb[2], ft);
   nee_walls(g, ft, dt / 2.0);
 }
 
@@ -396,7 +460,8 @@ static void step_family(const grid_t* g, const double bt[3], double* ft, double*
 static int run_impl(int nx, int ny, const double* x, const double* y, int per_x, int per_y,
                     double period_x, double period_y, double dt, double inv_tau, double A,
                     double eta, double Fx, double Fy, const double* u_wall, double offset,
-                    int scheme, const double* bt, double* phi, long nsteps) {
+                    int scheme, const double* bt, const double* bb, double* phi,
+                    long nsteps) {
   if (nx < 5 || ny < 5 || dt <= 0.0 || inv_tau < 0.0 || !phi || !x || !y) return 1;
   if (scheme != 1 && scheme != 2 && !(scheme == 3 && bt)) return 1;
   grid_t g;
@@ -426,8 +491,11 @@ static int run_impl(int nx, int ny, const double* x, const double* y, int per_x,
   double* R = (double*)malloc(n * sizeof(double));
   double* Fn = scheme == 3 ? (double*)malloc(n * sizeof(double)) : NULL;
   double* R2 = scheme == 3 ? (double*)malloc(n * sizeof(double)) : NULL;
+  double* Om0 = bb ? (double*)malloc(n * sizeof(double)) : NULL;
+  double* Om1 = bb ? (double*)malloc(n * sizeof(double)) : NULL;
   int rc = 0;
-  if (!g.mx || !g.my || !P || !Qp || !S || !R || (scheme == 3 && (!Fn || !R2))) {
+  if (!g.mx || !g.my || !P || !Qp || !S || !R || (scheme == 3 && (!Fn || !R2)) ||
+      (bb && (!Om0 || !Om1))) {
     rc = 2;
   } else {
     metric(nx, x, per_x, period_x, g.mx);
@@ -438,7 +506,7 @@ static int run_impl(int nx, int ny, const double* x, const double* y, int per_x,
       else if (scheme == 2)
         step_fdlbm2(&g, phi, P, Qp, S, R);
       else
-        step_family(&g, bt, phi, P, Fn, Qp, S, R, R2);
+        step_family(&g, bt, bb, phi, P, Fn, Qp, S, R, R2, Om0, Om1);
     }
   }
   free(g.mx);
@@ -449,6 +517,8 @@ static int run_impl(int nx, int ny, const double* x, const double* y, int per_x,
   free(R);
   free(Fn);
   free(R2);
+  free(Om0);
+  free(Om1);
   return rc;
 }
 
@@ -458,17 +528,18 @@ int oracle_run(int nx, int ny, const double* x, const double* y, int per_x, int 
                int scheme, double* phi, long nsteps) {
   if (scheme != 1 && scheme != 2) return 1;
   return run_impl(nx, ny, x, y, per_x, per_y, period_x, period_y, dt, inv_tau, A, eta, Fx, Fy,
-                  u_wall, offset, scheme, NULL, phi, nsteps);
+                  u_wall, offset, scheme, NULL, NULL, phi, nsteps);
 }
 
-/* The eq 2.13 family (step_family) with gradient weights bt[3]. */
+/* The eq 2.13 family (step_family) with gradient weights bt[3] and
+ * collision weights bb[3] (NULL: (1/2, 0, 1/2) in the explicit form). */
 int oracle_run_family(int nx, int ny, const double* x, const double* y, int per_x, int per_y,
                       double period_x, double period_y, double dt, double inv_tau, double A,
                       double eta, double Fx, double Fy, const double* u_wall, double offset,
-                      const double* bt, double* phi, long nsteps) {
+                      const double* bt, const double* bb, double* phi, long nsteps) {
   if (!bt) return 1;
   return run_impl(nx, ny, x, y, per_x, per_y, period_x, period_y, dt, inv_tau, A, eta, Fx, Fy,
-                  u_wall, offset, 3, bt, phi, nsteps);
+                  u_wall, offset, 3, bt, bb, phi, nsteps);
 }
 
 /* Initial populations (Sec. 3): f~ = f^eq(rho, u), optionally minus the
