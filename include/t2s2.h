@@ -72,12 +72,18 @@ extern "C" {
  * intermediate stage at t + A dt (A = 1/2: T2S2-FDLBM1, A = 0: T1S2).
  * T2S2_FDLBM2: eq 5.23, f~^{n+1} = f~^{+,n} + dt/2 (L(f^n) + L(f^{n+1})) with
  * f^{n+1} predicted by a full-step characteristic update; A is not used.
- * T2S2_FAMILY: the eq 2.13 family with the collision weights of eqs 2.21
- * and 5.21 (Bbar = (1/2, 0, 1/2)) and gradient weights btilde:
- *   f~^{n+1} = f~^{+,n} + dt [B~0 L(f^n) + B~1 L(f*) + B~2 L(f^{n+1})],
- * f* predicted as in T2S2_FDLBM1 (h = A dt) and f^{n+1} as in T2S2_FDLBM2.
- * btilde = (0, 1, 0) is T2S2_FDLBM1 and (1/2, 0, 1/2) T2S2_FDLBM2;
- * A B~1 + B~2 = 1/2 gives second order in time (eq 2.14b). */
+ * T2S2_FAMILY: the eq 2.13 family with gradient weights btilde and
+ * collision weights bbar,
+ *   f^{n+1} - B-2 dt Omega(f^{n+1}) = f^n + dt [B-0 Omega(f^n) + B-1 Omega(f*)]
+ *                 + dt [B~0 L(f^n) + B~1 L(f*) + B~2 L(f^{n+1})],
+ * f* predicted as in T2S2_FDLBM1 (h = A dt), f^{n+1} on the right as in
+ * T2S2_FDLBM2; the left side is solved node by node through the moments
+ * and the state stays f~ = f - (dt/2) Omega (eq 2.19).  With the collision
+ * weights of eqs 2.21 and 5.21, bbar = (1/2, 0, 1/2), this is the explicit
+ *   f~^{n+1} = f~^{+,n} + dt [B~0 L(f^n) + B~1 L(f*) + B~2 L(f^{n+1})];
+ * btilde = (0, 1, 0) is then T2S2_FDLBM1 and (1/2, 0, 1/2) T2S2_FDLBM2.
+ * A B~1 + B~2 = 1/2 and A B-1 + B-2 = 1/2 give second order in time
+ * (eq 2.14b). */
 #define T2S2_FDLBM1 1
 #define T2S2_FDLBM2 2
 #define T2S2_FAMILY 3
@@ -105,6 +111,9 @@ typedef struct t2s2_config {
   double btilde[3];     /* T2S2_FAMILY only: (B~0, B~1, B~2), each >= 0,
                            B~0, B~1 <= 1, B~2 <= 1/2, summing to 1 within
                            1e-12 (eq 2.14a); ignored by the other schemes */
+  double bbar[3];       /* T2S2_FAMILY only: (B-0, B-1, B-2) in the same
+                           ranges; all zero reads as (1/2, 0, 1/2); ignored
+                           by the other schemes */
 } t2s2_config;
 
 typedef struct t2s2_ctx t2s2_ctx;
@@ -319,7 +328,8 @@ int t2s2_adjoint_load(t2s2_ctx* ctx, const double* in, void* lam);
  *                    h = A dt (the step t2s2_step takes for T2S2_FDLBM1);
  *   T2S2_STAB_FDLBM2 the exact linearisation of the eq 5.23 step;
  *   T2S2_STAB_FAMILY the exact linearisation of the T2S2_FAMILY step with
- *                    gradient weights btilde and h = A dt.
+ *                    gradient weights btilde, collision weights bbar and
+ *                    h = A dt.
  * S is the symbol of the mixed difference (eq 4.8 with the imaginary unit
  * in its exponentials).  Modes: theta_y = k_y dx in [0, pi] (nk points);
  * theta_x in [0, pi] (nk points) or, with full_kx, in [-pi, pi] (2 nk - 1
@@ -344,6 +354,10 @@ typedef struct t2s2_stability_params {
   int squarings;   /* 1..60 */
   double btilde[3]; /* T2S2_STAB_FAMILY: (B~0, B~1, B~2), finite (any
                        weights; the step's own ranges are not imposed) */
+  double bbar[3];   /* T2S2_STAB_FAMILY: (B-0, B-1, B-2), finite; all zero
+                       reads as (1/2, 0, 1/2).  The implicit weight divides
+                       by 1 + B-2 omega: a point where that is 0 gets a
+                       non-finite radius */
 } t2s2_stability_params;
 
 int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, const double* r,

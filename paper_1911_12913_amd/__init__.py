@@ -51,6 +51,7 @@ class Config(ctypes.Structure):
         ("storage", ctypes.c_int),
         ("scheme", ctypes.c_int),
         ("btilde", ctypes.c_double * 3),
+        ("bbar", ctypes.c_double * 3),
     ]
 
 
@@ -68,6 +69,7 @@ class StabilityParams(ctypes.Structure):
         ("full_kx", ctypes.c_int),
         ("squarings", ctypes.c_int),
         ("btilde", ctypes.c_double * 3),
+        ("bbar", ctypes.c_double * 3),
     ]
 
 
@@ -157,10 +159,12 @@ def _check(rc: int):
 def make_config(*, nu: float, cfl: float = 0.0, dt: float = 0.0, eta: float = 0.01,
                 A: float = 0.5, force=(0.0, 0.0), u_wall=None, periodic_x: bool = True,
                 periodic_y: bool = True, period_x: float = 0.0, period_y: float = 0.0,
-                storage="f64", scheme: int = 1, btilde=(0.0, 1.0, 0.0)) -> Config:
+                storage="f64", scheme: int = 1, btilde=(0.0, 1.0, 0.0),
+                bbar=(0.5, 0.0, 0.5)) -> Config:
     """scheme 1: T2S2-FDLBM1 family (A = 1/2 FDLBM1, A = 0 T1S2); scheme 2:
     T2S2-FDLBM2; scheme 3: the eq 2.13 family with gradient weights btilde
-    on L(f^n), L(f*), L(f^{n+1})."""
+    on L(f^n), L(f*), L(f^{n+1}) and collision weights bbar on Omega(f^n),
+    Omega(f*), Omega(f^{n+1})."""
     cfg = Config()
     cfg.nu = float(nu)
     cfg.cfl = float(cfl)
@@ -180,6 +184,7 @@ def make_config(*, nu: float, cfl: float = 0.0, dt: float = 0.0, eta: float = 0.
     cfg.scheme = int(scheme)
     for k in range(3):
         cfg.btilde[k] = float(btilde[k])
+        cfg.bbar[k] = float(bbar[k])
     return cfg
 
 
@@ -467,8 +472,8 @@ def context_for_case(case, storage="f64", device=None, stream=None, **overrides)
 
 
 def stability_map(model, omega, r, *, eta, u=(0.0, 0.0), A=0.5, b2bar=0.5, b2tilde=0.0,
-                  nk=33, full_kx=True, squarings=30, btilde=(0.0, 1.0, 0.0), device=None,
-                  stream=None):
+                  nk=33, full_kx=True, squarings=30, btilde=(0.0, 1.0, 0.0),
+                  bbar=(0.5, 0.0, 0.5), device=None, stream=None):
     """Largest spectral radius of the growth matrix over the mode grid for
     each (omega[i], r[i]) (t2s2_stability_map); returns a device tensor."""
     import torch
@@ -487,6 +492,7 @@ def stability_map(model, omega, r, *, eta, u=(0.0, 0.0), A=0.5, b2bar=0.5, b2til
     prm.nk, prm.full_kx, prm.squarings = int(nk), int(bool(full_kx)), int(squarings)
     for k in range(3):
         prm.btilde[k] = float(btilde[k])
+        prm.bbar[k] = float(bbar[k])
     with torch.cuda.device(dev):
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         _check(lib.t2s2_stability_map(ctypes.byref(prm), w.data_ptr(), rr.data_ptr(), w.numel(),

@@ -139,7 +139,10 @@ void plan_strips(StepParams& p, int storage) {
 // grid size, or -1 if the kernel cannot be resident.
 int plan_blocks(StepParams& p, int storage, int cus) {
   const bool walls = !p.per_x || !p.per_y;
-  const int per_cu = step_blocks_per_cu(storage, p.has_force != 0, walls, p.single ? 0 : p.scheme);
+  // Kernel scheme codes: 0 the single-stencil step, 4 the family with
+  // collision weights other than (1/2, 0, 1/2).
+  const int kscheme = p.single ? 0 : (p.scheme == 3 && p.gen_bbar ? 4 : p.scheme);
+  const int per_cu = step_blocks_per_cu(storage, p.has_force != 0, walls, kscheme);
   if (per_cu < 1) return -1;
   const long long rows = static_cast<long long>(p.nunits) * p.ny;
   const long long slots = static_cast<long long>(cus) * per_cu;
@@ -270,6 +273,14 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
         return fail(T2S2_ERR_INVALID_ARG, "btilde: B~0, B~1 in [0,1], B~2 in [0,1/2]");
     if (!(std::fabs(b[0] + b[1] + b[2] - 1.0) <= 1e-12))
       return fail(T2S2_ERR_INVALID_ARG, "btilde must sum to 1 (eq 2.14a)");
+    const double* bb = cfg->bbar;
+    if (!(bb[0] == 0.0 && bb[1] == 0.0 && bb[2] == 0.0)) {
+      for (int k = 0; k < 3; ++k)
+        if (!(bb[k] >= 0.0 && bb[k] <= (k == 2 ? 0.5 : 1.0)))
+          return fail(T2S2_ERR_INVALID_ARG, "bbar: B-0, B-1 in [0,1], B-2 in [0,1/2]");
+      if (!(std::fabs(bb[0] + bb[1] + bb[2] - 1.0) <= 1e-12))
+        return fail(T2S2_ERR_INVALID_ARG, "bbar must sum to 1 (eq 2.14a)");
+    }
   }
   // The step kernel addresses a population plane with 32-bit byte offsets.
   if (static_cast<long long>(ny) * ((nx + 63) / 64 * 64) *
@@ -335,6 +346,37 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   p.cUe = w / (2.0 + w);
   p.cUF = dt / (2.0 + w);
   for (int k = 0; k < 3; ++k) p.b[k] = scheme == 3 ? cfg->btilde[k] : (k == 1 ? 1.0 : 0.0);
+  // Collision weights of the family (all zero: (1/2, 0, 1/2)).  Other than
+  // (1/2, 0, 1/2), with w = dt / tau and Omega(f) dt = w (f^eq - f) + dt F:
+  //   Q2 = f^n + B-0 dt Omega(f^n), f^n = cUg f~ + cUe f^eq + cUF F:
+  //     cQ2g = (1 - B-0 w) cUg, cQ2e = (1 - B-0 w) cUe + B-0 w,
+  //     cQ2F = (1 - B-0 w) cUF + B-0 dt;
+  //   V = B-1 dt Omega(f*): cV = B-1 w, cVF = B-1 dt;
+  //   f^{n+1} = [Y + B-2 (w f^eq + dt F)] / (1 + B-2 w) and
+  //   f~ = f^{n+1} + (w/2) (f^{n+1} - f^eq) - (dt/2) F (eq 2.19):
+  //     aY = (1 + w/2) / (1 + B-2 w), aE = w (B-2 - 1/2) / (1 + B-2 w),
+  //     aF = dt (B-2 - 1/2) / (1 + B-2 w).
+  {
+    const double* bb = cfg->bbar;
+    const bool zero = bb[0] == 0.0 && bb[1] == 0.0 && bb[2] == 0.0;
+    const double b0 = zero ? 0.5 : bb[0], b1 = zero ? 0.0 : bb[1], b2 = zero ? 0.5 : bb[2];
+    p.gen_bbar = (scheme == 3 && !(b0 == 0.5 && b1 == 0.0 && b2 == 0.5)) ? 1 : 0;
+    p.bbar[0] = b0;
+    p.bbar[1] = b1;
+    p.bbar[2] = b2;
+    p.cQ2g = (1.0 - b0 * w) * p.cUg;
+    p.cQ2e = (1.0 - b0 * w) * p.cUe + b0 * w;
+    p.cQ2F = (1.0 - b0 * w) * p.cUF + b0 * dt;
+    p.cV = b1 * w;
+    p.cVF = b1 * dt;
+    p.aY = (1.0 + 0.5 * w) / (1.0 + b2 * w);
+    p.aE = w * (b2 - 0.5) / (1.0 + b2 * w);
+    p.aF = dt * (b2 - 0.5) / (1.0 + b2 * w);
+    p.b2dt = b2 * dt;
+    c->cfg.bbar[0] = b0;
+    c->cfg.bbar[1] = b1;
+    c->cfg.bbar[2] = b2;
+  }
   {
     const double wc[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
     p.c64.cPg = p.cPg;
@@ -348,7 +390,13 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
       p.c64.kR[k] = p.cRe * wc[k];
       p.c64.kU[k] = p.cUe * wc[k];
       p.c64.b[k] = p.b[k];
+      p.c64.kQ2[k] = p.cQ2e * wc[k];
+      p.c64.kV[k] = p.cV * wc[k];
+      p.c64.kA[k] = p.aE * wc[k];
     }
+    p.c64.cQ2g = p.cQ2g;
+    p.c64.cV = p.cV;
+    p.c64.aY = p.aY;
     p.c32.cPg = static_cast<float>(p.c64.cPg);
     p.c32.cQg = static_cast<float>(p.c64.cQg);
     p.c32.cRs = static_cast<float>(p.c64.cRs);
@@ -360,7 +408,13 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
       p.c32.kR[k] = static_cast<float>(p.c64.kR[k]);
       p.c32.kU[k] = static_cast<float>(p.c64.kU[k]);
       p.c32.b[k] = static_cast<float>(p.c64.b[k]);
+      p.c32.kQ2[k] = static_cast<float>(p.c64.kQ2[k]);
+      p.c32.kV[k] = static_cast<float>(p.c64.kV[k]);
+      p.c32.kA[k] = static_cast<float>(p.c64.kA[k]);
     }
+    p.c32.cQ2g = static_cast<float>(p.c64.cQ2g);
+    p.c32.cV = static_cast<float>(p.c64.cV);
+    p.c32.aY = static_cast<float>(p.c64.aY);
   }
   p.half_dt = 0.5 * dt;
   p.half_h = 0.5 * A * dt;
@@ -897,6 +951,10 @@ int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, co
                                           std::isfinite(prm->btilde[1]) &&
                                           std::isfinite(prm->btilde[2])))
     return fail(T2S2_ERR_INVALID_ARG, "non-finite btilde");
+  if (prm->model == T2S2_STAB_FAMILY && !(std::isfinite(prm->bbar[0]) &&
+                                          std::isfinite(prm->bbar[1]) &&
+                                          std::isfinite(prm->bbar[2])))
+    return fail(T2S2_ERR_INVALID_ARG, "non-finite bbar");
   if (prm->nk < 2 || prm->nk > 257) return fail(T2S2_ERR_INVALID_ARG, "nk not in [2, 257]");
   if (prm->squarings < 1 || prm->squarings > 60)
     return fail(T2S2_ERR_INVALID_ARG, "squarings not in [1, 60]");
@@ -919,6 +977,15 @@ int t2s2_stability_map(const t2s2_stability_params* prm, const double* omega, co
   a.thx0 = prm->full_kx ? -pi : 0.0;
   a.squarings = prm->squarings;
   for (int k = 0; k < 3; ++k) a.bt[k] = prm->model == T2S2_STAB_FAMILY ? prm->btilde[k] : 0.0;
+  {
+    const double* bb = prm->bbar;
+    const bool zero = bb[0] == 0.0 && bb[1] == 0.0 && bb[2] == 0.0;
+    a.bb[0] = zero ? 0.5 : bb[0];
+    a.bb[1] = zero ? 0.0 : bb[1];
+    a.bb[2] = zero ? 0.5 : bb[2];
+    a.gen_bb = prm->model == T2S2_STAB_FAMILY &&
+               !(a.bb[0] == 0.5 && a.bb[1] == 0.0 && a.bb[2] == 0.5);
+  }
   hipError_t e = launch_stability(a, omega, r, npoints, radius, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "stability map");
   return T2S2_OK;

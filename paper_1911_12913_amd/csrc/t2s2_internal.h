@@ -85,6 +85,16 @@ struct StepParams {
   double cRs, cRe, cRF;  // R = cRs S + cRe (feq* - w) + cRF F*
   double cUg, cUe, cUF;  // f at h = dt: cUg X + cUe (feq(X) - w) + cUF F(X)
   double b[3];           // gradient weights of L(f^n), L(f*), L(f^{n+1})
+  // Collision weights of the family other than (1/2, 0, 1/2) (gen_bbar):
+  //   Q2 = f^n + B-0 dt Omega(f^n) = cQ2g g + cQ2e (feq - w) + cQ2F F
+  //     (the base of the update, in place of Q),
+  //   V  = B-1 dt Omega(f*) = cV ((feq* - w) - (f* - w)) + cVF F*,
+  //   and the new state from Y = Q2 + V + dt L(T), the implicit weight
+  //   solved through Y's moments (velocity shift b2dt = B-2 dt):
+  //   f~ = aY Y + aE (feq - w) + aF F.
+  int gen_bbar;
+  double bbar[3];
+  double cQ2g, cQ2e, cQ2F, cV, cVF, aY, aE, aF, b2dt;
   double half_dt, half_h;
   double Fx, Fy;
   double uw[4][2];
@@ -99,6 +109,10 @@ struct StepParams {
     Real cPg, cQg, cRs, A, cU;
     Real kP[3], kQ[3], kR[3], kU[3];
     Real b[3];
+    // gen_bbar: cQ2g, cV, aY and per weight class kQ2[c] = cQ2e w_c,
+    // kV[c] = cV w_c, kA[c] = aE w_c.
+    Real cQ2g, cV, aY;
+    Real kQ2[3], kV[3], kA[3];
   };
   Coef<double> c64;
   Coef<float> c32;
@@ -116,9 +130,12 @@ struct AuxParams {
 // Von Neumann stability maps (t2s2_stability.hip).
 struct StabArgs {
   int model;  // 0: eq 4.7; 1: eq 2.23 step, exact; 2: eq 5.23 step, exact;
-              // 3: the eq 2.13 family step with gradient weights bt, exact
+              // 3: the eq 2.13 family step with gradient weights bt and
+              //    collision weights bb (gen_bb: other than (1/2, 0, 1/2)), exact
   double eta, A, b2bar, b2tilde, ux, uy;
   double bt[3];
+  double bb[3];
+  int gen_bb;
   int nkx, nky;             // k grid: theta_x = thx0 + i dthx, theta_y = j dthy
   double thx0, dthx, dthy;
   int squarings;
@@ -159,7 +176,8 @@ constexpr int kAdjMaxBlocks = 1024;
 hipError_t launch_step(int storage, const StepParams& p, int grid, hipStream_t s);
 hipError_t launch_step_save_s(int storage, const StepParams& p, int grid, hipStream_t s);
 // Resident step-kernel blocks per CU for this variant (-1 on error); scheme
-// 0 is the single-stencil (A = 0) kernel.
+// 0 is the single-stencil (A = 0) kernel, 4 the family (scheme 3) with
+// collision weights other than (1/2, 0, 1/2).
 int step_blocks_per_cu(int storage, bool force, bool walls, int scheme);
 hipError_t launch_init_macro(int storage, const AuxParams& a, void* state, const double* rho,
                              const double* ux, const double* uy, const double* grad,

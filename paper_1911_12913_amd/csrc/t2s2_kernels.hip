@@ -214,7 +214,7 @@ template <typename Store, bool kForce, bool kWalls, int kScheme>
 constexpr int kMinWaves =
     sizeof(typename Cvt<Store>::R) == 8
         ? ((kScheme == 1 || (kScheme == 2 && !kWalls)) ? 2 : 1)
-        : (kScheme == 3 ? 2
+        : (kScheme >= 3 ? 2
                         : ((kScheme == 2 || kForce || kBf16Bits<Store> || kStochastic<Store> ||
                             (kWalls && !std::is_same<Store, float>::value))
                                ? 3
@@ -248,7 +248,16 @@ constexpr int kPPlanes =
 //     L is linear, so the two gradients are taken as one, of T = f^n + R;
 //   kScheme 3: the eq 2.13 family, f~^{n+1} = Q + dt L(T) with
 //     T = b0 f^n + b1 f* + b2 f^{n+1}, f* predicted as in scheme 1 and
-//     f^{n+1} as in scheme 2.
+//     f^{n+1} as in scheme 2;
+//   kScheme 4: the family with collision weights other than (1/2, 0, 1/2)
+//     (p.gen_bbar; host scheme 3): the base is Q2 = f^n + B-0 dt Omega(f^n)
+//     and V = B-1 dt Omega(f*) is added, and the new state is formed from
+//     Y = Q2 + V + dt L(T) by solving the implicit weight B-2 through Y's
+//     moments.  V of a node is formed in phase 2 from that node's f* and
+//     used by phase 3 of the same wave, in registers: the waves take the
+//     phase-2 rows in the order that makes each one's phase-2 row the row it
+//     outputs (in the same iteration for waves 2 and 3, in the next for
+//     waves 0 and 1).
 template <typename Store, bool kForce, bool kWalls, int kScheme, bool kSaveS = false>
 __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWaves<Store, kForce, kWalls, kScheme>)) void step_kernel(
     StepParams p) {
@@ -340,6 +349,13 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
     Real qA[kQ], qB[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) qA[q] = qB[q] = Real(0);
+    // The family's V = B-1 dt Omega(f*) of this wave's phase-2 rows of this
+    // and of the previous iteration (kScheme 4 only).
+    Real vA[kQ], vB[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) vA[q] = vB[q] = Real(0);
+    constexpr bool kFamily = kScheme >= 3;
+    constexpr bool gen_bbar = kScheme == 4;
 
     // Iterations come in pairs (one per prefetch buffer); a trailing extra
     // iteration only reloads clamped rows and stores nothing (its rows fail
@@ -365,7 +381,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
     load_row(y0 - kHalo + kRowsPerIter + t, gB);
     __syncthreads();  // ring zero-fill / previous piece complete
 
-    auto iteration = [&](const int it, Store (&gb)[kQ], Real (&qnew)[kQ], const Real (&qold)[kQ]) {
+    auto iteration = [&](const int it, Store (&gb)[kQ], Real (&qnew)[kQ], const Real (&qold)[kQ],
+                         Real (&vnew)[kQ], const Real (&vold)[kQ]) {
       const int p0 = y0 - kHalo + kRowsPerIter * it;
 
       // ---- phase 1: P (to LDS) and Q (registers) of row p0 + t; for
@@ -411,7 +428,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
           }
           slotP[q * kLanes + lane] = kScheme == 2 ? Qq : Pq;
           if (kScheme == 2 && !kReloadFn && q > 0) slotP[(kQ + q - 1) * kLanes + lane] = Pq;
-          if (kScheme == 3) {
+          if (kFamily) {
             slotP[(kQ + q) * kLanes + lane] = Qq;
             if (q > 0) {
               Real Uq = k.cU * g[q] + k.kU[wclass(q)] * E;  // f^n
@@ -420,6 +437,11 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
             }
           }
           qnew[q] = Qq;
+          if constexpr (gen_bbar) {  // Q2 = f^n + B-0 dt Omega(f^n)
+            Real Q2 = k.cQ2g * g[q] + k.kQ2[wclass(q)] * E;
+            if (kForce) Q2 += static_cast<Real>(p.cQ2F) * Fq;
+            qnew[q] = Q2;
+          }
         }
       }
       __syncthreads();
@@ -429,7 +451,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
       // take neighbouring lanes' centre values); only interior lanes 2..61
       // store.
       {
-        const int r = p0 - 2 + t;
+        const int r = p0 - 2 + (gen_bbar ? (t + 2) % kRowsPerIter : t);
         const bool row_ok =
             r >= y0 - 2 && r < y1 + 2 && (p.per_y || (r >= 1 && r <= ny - 2));
         if (row_ok) {
@@ -445,9 +467,12 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
           // A prediction along the characteristics from ring planes
           // [base, base + 9): S = centre + fac L(centre); then f at the
           // predicted time, R = cs S + ke E (+ cf F), from S's moments with
-          // force shift hf.
+          // force shift hf.  With want_v, also V = B-1 dt Omega(R) (all
+          // nine directions; R[0] stays 0, the rest direction has no
+          // gradient).
           auto predict = [&](int base, Real fac, Real cs, const Real* ke, double cf, double hf,
-                             Real (&S)[kQ], Real (&R)[kQ], Real& rho, Real& ux, Real& uy) {
+                             Real (&S)[kQ], Real (&R)[kQ], Real& rho, Real& ux, Real& uy,
+                             bool want_v, Real (&V)[kQ]) {
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
               const int pq = (base + q) * kLanes;
@@ -480,9 +505,23 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
               if (kForce) Rq += static_cast<Real>(cf) * force_term(q, p, ux, uy, E);
               R[q] = Rq;
             }
+            if (want_v) {
+              // Omega(f*) dt = w (f^eq* - f*) + dt F*, in deviations from w.
+#pragma unroll
+              for (int q = 0; q < kQ; ++q) {
+                const Real E = d + rho * X[q];
+                Real Fq = Real(0);
+                if (kForce) Fq = force_term(q, p, ux, uy, E);
+                Real Rq = cs * S[q] + ke[wclass(q)] * E;
+                if (kForce) Rq += static_cast<Real>(cf) * Fq;
+                Real Vq = k.kV[wclass(q)] * E - k.cV * Rq;
+                if (kForce) Vq += static_cast<Real>(p.cVF) * Fq;
+                V[q] = Vq;
+              }
+            }
           };
           Real S[kQ], R[kQ], rho, ux, uy;
-          predict(0, k.A, k.cRs, k.kR, p.cRF, p.half_h, S, R, rho, ux, uy);
+          predict(0, k.A, k.cRs, k.kR, p.cRF, p.half_h, S, R, rho, ux, uy, gen_bbar, vnew);
           if (kSaveS && lane_o && col_interior && r >= y0 && r < y1) {
             Real* sv = static_cast<Real*>(p.save_s);
             const unsigned boff =
@@ -495,9 +534,10 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
           Real R2[kQ], rho2 = Real(1), ux2 = Real(0), uy2 = Real(0);
 #pragma unroll
           for (int q = 0; q < kQ; ++q) R2[q] = Real(0);
-          if constexpr (kScheme == 3) {
+          if constexpr (kFamily) {
             Real S2[kQ];
-            predict(kQ, Real(1), k.cU, k.kU, p.cUF, p.half_dt, S2, R2, rho2, ux2, uy2);
+            predict(kQ, Real(1), k.cU, k.kU, p.cUF, p.half_dt, S2, R2, rho2, ux2, uy2, false,
+                    S2);
           }
           // f^n of this node from the reloaded row (kReloadFn), with the
           // expressions of phase 1.
@@ -534,7 +574,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
           auto t_of = [&](int q, int row, int ln, Real r1, Real r2) {
             const Real* slot = ringP + (row & (kRing - 1)) * kNP * kLanes + ln;
             if (kScheme == 2) return r1 + (kReloadFn ? fn[q] : slot[(kQ + q - 1) * kLanes]);
-            if (kScheme == 3)
+            if (kFamily)
               return k.b[0] * slot[(2 * kQ + q - 1) * kLanes] + k.b[1] * r1 + k.b[2] * r2;
             return r1;
           };
@@ -561,7 +601,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
                             static_cast<double>(uy), ub, vb, sh);
 #pragma unroll
                   for (int q = 0; q < kQ; ++q) sh2[q] = Real(0);
-                  if constexpr (kScheme == 3)
+                  if constexpr (kFamily)
                     nee_shift(static_cast<double>(rho2), static_cast<double>(ux2),
                               static_cast<double>(uy2), ub, vb, sh2);
                   Real* slotW = dy == 1 ? topR : ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
@@ -592,12 +632,17 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
             if (kWalls && !p.per_y && o + k - 2 == ny - 1) rb[k] = topR + lane;
           }
           Real out[kQ];
+          // V of this row: formed in this iteration's phase 2 by waves 2
+          // and 3, in the previous one's by waves 0 and 1.
+          const bool v_now = t >= 2;
           out[0] = qold[0];
+          if constexpr (gen_bbar) out[0] += v_now ? vnew[0] : vold[0];
 #pragma unroll
           for (int q = 1; q < kQ; ++q) {
             const int pq = (q - 1) * kLanes;
             const Real centre = rb[2][pq];
             Real acc = kScheme == 2 ? Real(0) : qold[q];
+            if constexpr (gen_bbar) acc += v_now ? vnew[q] : vold[q];
             if (ex_of(q) > 0) acc = x_taps<0>(wxr, centre, acc);
             if (ex_of(q) < 0) acc = x_taps<1>(wxr, centre, acc);
             if (ey_of(q) != 0) {
@@ -606,6 +651,30 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
               for (int k = 0; k < kTaps; ++k) acc += wyr[sy * kTaps + k] * rb[k + sy][pq];
             }
             out[q] = kScheme == 2 ? qold[q] + Real(0.5) * acc : acc;
+          }
+          if constexpr (gen_bbar) {
+            // The implicit weight: f^{n+1} has Y's density and Y's momentum
+            // plus B-2 dt rho F; the state is f~ = aY Y + aE (f^eq - w) + aF F
+            // at that (rho, u).
+            const auto& k = coef<Real>(p);
+            double s, jx, jy;
+            moment_sums(out, s, jx, jy);
+            Real rho, ux, uy;
+            velocity(s, jx, jy, rho, ux, uy);
+            if (kForce) {
+              ux += static_cast<Real>(p.b2dt * p.Fx);
+              uy += static_cast<Real>(p.b2dt * p.Fy);
+            }
+            const Real d = static_cast<Real>(s);
+            Real X[kQ];
+            eq_brackets(ux, uy, X);
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+              const Real E = d + rho * X[q];
+              Real o = k.aY * out[q] + k.kA[wclass(q)] * E;
+              if (kForce) o += static_cast<Real>(p.aF) * force_term(q, p, ux, uy, E);
+              out[q] = o;
+            }
           }
           if (lane_o && col_interior) {
             const unsigned boff =
@@ -618,8 +687,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
     };
 
     for (int it = 0; it < niter; it += 2) {
-      iteration(it, gA, qA, qB);
-      iteration(it + 1, gB, qB, qA);
+      iteration(it, gA, qA, qB, vA, vB);
+      iteration(it + 1, gB, qB, qA, vB, vA);
     }
     __syncthreads();  // the next piece reuses the rings; the piece's stores are visible
     if (kWalls) piece_walls(p, dst, x0, x1, y0, y1, threadIdx.x % kBlockThreads, kBlockThreads);
@@ -1336,6 +1405,8 @@ hipError_t launch_step_t(const StepParams& p, int grid, hipStream_t s) {
     return hipErrorInvalidValue;  // the stochastic forms run scheme 1 only
   else if (p.scheme == 2)
     launch_fused<Store, 2>(p, g, b, s, walls);
+  else if (p.gen_bbar)
+    launch_fused<Store, 4>(p, g, b, s, walls);
   else
     launch_fused<Store, 3>(p, g, b, s, walls);
   return hipGetLastError();
@@ -1412,6 +1483,7 @@ int occupancy_t(bool force, bool walls, int scheme) {
     return -1;  // scheme 1 only
   } else {
     if (scheme == 2) return occupancy_s<Store, 2>(force, walls);
+    if (scheme == 4) return occupancy_s<Store, 4>(force, walls);
     return occupancy_s<Store, 3>(force, walls);
   }
 }

@@ -13,6 +13,14 @@
 //     G = J_Q - (rS/2) (J_f + J_R1 (I - rS) J_Q);
 //   model 3: the exact linearisation of the eq 2.13 family step:
 //     G = J_Q - rS (b0 J_f + b1 J_R (I - A rS) J_P + b2 J_R1 (I - rS) J_Q);
+//     with collision weights (B-0, B-1, B-2) other than (1/2, 0, 1/2)
+//     (dt Omega(f) = w (Gamma - I) f, unforced):
+//     Y = J_f + w (Gamma - I) (B-0 J_f + B-1 J_R (I - A rS) J_P)
+//         - rS (b0 J_f + b1 J_R (I - A rS) J_P + b2 J_R1 (I - rS) J_Q),
+//     G = (aY I + aE Gamma) Y with aY = (1 + w/2) / (1 + B-2 w) and
+//     aE = w (B-2 - 1/2) / (1 + B-2 w): the implicit weight solved (Gamma
+//     is a projection, Gamma^2 = Gamma: f^eq keeps the moments it is built
+//     from) and the state taken as f~ = f - (dt/2) Omega(f) (eq 2.19);
 // with Gamma = d f^eq / d f, J_X = c_Xg I + c_Xe Gamma, and S the symbol of
 // dx xi_q . D of the mixed difference (eq 4.8, imaginary unit restored in
 // the exponentials).  The advection symbol multiplies from the left (it
@@ -83,7 +91,7 @@ __device__ inline void for_elems(int lane, F f) {
 __global__ __launch_bounds__(64) void stability_kernel(StabArgs a, const double* omega_p,
                                                         const double* r_p, double* radius) {
   __shared__ double gam[kN2];
-  __shared__ cplx X[kN2], T[kN2], T2[kN2];
+  __shared__ cplx X[kN2], T[kN2], T2[kN2], U[kN2];
   __shared__ cplx sym[kN];
   const int lane = threadIdx.x;
   const int point = blockIdx.x;
@@ -185,9 +193,37 @@ __global__ __launch_bounds__(64) void stability_kernel(StabArgs a, const double*
         const double d = i == j ? 1.0 : 0.0, g = gam[i * kN + j];
         cplx m = cadd(cscale(m1, a.bt[1]), cscale(m2, a.bt[2]));
         m = cadd(m, {a.bt[0] * (cFg * d + cFe * g), 0.0});
-        X[i * kN + j] = csub({cQg * d + cQe * g, 0.0}, cmul(cscale(sym[i], r), m));
+        // The base: J_Q, or J_f with the collision weights' terms added below.
+        const double base = a.gen_bb ? cFg * d + cFe * g : cQg * d + cQe * g;
+        X[i * kN + j] = csub({base, 0.0}, cmul(cscale(sym[i], r), m));
+        U[i * kN + j] = m1;  // J_R (I - A rS) J_P, the Jacobian of f*
       });
       __syncthreads();
+      if (a.gen_bb) {
+        // X += w (Gamma - I) (B-0 J_f + B-1 U)
+        for_elems(lane, [&](int i, int j) {
+          cplx acc{0.0, 0.0};
+          for (int k = 0; k < kN; ++k) {
+            const double gik = gam[i * kN + k] - (i == k ? 1.0 : 0.0);
+            const double jf = cFg * (k == j ? 1.0 : 0.0) + cFe * gam[k * kN + j];
+            acc = cadd(acc, cscale(cadd({a.bb[0] * jf, 0.0}, cscale(U[k * kN + j], a.bb[1])), gik));
+          }
+          X[i * kN + j] = cadd(X[i * kN + j], cscale(acc, w));
+        });
+        __syncthreads();
+        // G = (aY I + aE Gamma) X
+        const double aY = (1 + 0.5 * w) / (1 + a.bb[2] * w);
+        const double aE = w * (a.bb[2] - 0.5) / (1 + a.bb[2] * w);
+        for_elems(lane, [&](int i, int j) {
+          cplx acc{0.0, 0.0};
+          for (int k = 0; k < kN; ++k)
+            acc = cadd(acc, cscale(X[k * kN + j], aY * (i == k ? 1.0 : 0.0) + aE * gam[i * kN + k]));
+          T[i * kN + j] = acc;
+        });
+        __syncthreads();
+        for_elems(lane, [&](int i, int j) { X[i * kN + j] = T[i * kN + j]; });
+        __syncthreads();
+      }
     } else {
       // T = (I - c rS) J, with (c, J) = (A, J_P) for model 1 and (1, J_Q) for model 2.
       const double cs = a.model == 1 ? A : 1.0;

@@ -30,10 +30,11 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_config_struct_layout():
-    # 5 doubles, force[2], u_wall[4][2], 2 ints, 2 doubles, 2 ints, btilde[3]
-    assert ctypes.sizeof(t2s2.Config) == 8 * 5 + 16 + 64 + 8 + 16 + 8 + 24
+    # 5 doubles, force[2], u_wall[4][2], 2 ints, 2 doubles, 2 ints, btilde[3], bbar[3]
+    assert ctypes.sizeof(t2s2.Config) == 8 * 5 + 16 + 64 + 8 + 16 + 8 + 24 + 24
     assert t2s2.Config.scheme.offset == 8 * 5 + 16 + 64 + 8 + 16 + 4
     assert t2s2.Config.btilde.offset == 8 * 5 + 16 + 64 + 8 + 16 + 8
+    assert t2s2.Config.bbar.offset == 8 * 5 + 16 + 64 + 8 + 16 + 8 + 24
 
 
 def test_scheme_validation():
@@ -51,8 +52,18 @@ def test_scheme_validation():
         assert (rc == t2s2.OK) == ok, bt
         if h.value:
             lib.t2s2_destroy(h)
-    # the other schemes ignore btilde
-    rc, h = _create(_good_cfg(scheme=1, btilde=(9.0, 9.0, 9.0)), _axis(20), _axis(20))
+    # the family's collision weights: the same ranges; all zero is (1/2, 0, 1/2)
+    for bb, ok in (((0.25, 0.5, 0.25), True), ((1.0, 0.0, 0.0), True), ((0.0, 0.0, 0.0), True),
+                   ((0.0, 1.0, 0.0), True), ((0.2, 0.2, 0.2), False), ((0.0, 0.4, 0.6), False),
+                   ((1.1, -0.1, 0.0), False), ((0.5, 0.0, float("nan")), False)):
+        rc, h = _create(_good_cfg(scheme=3, btilde=(0.0, 1.0, 0.0), bbar=bb), _axis(20),
+                        _axis(20))
+        assert (rc == t2s2.OK) == ok, bb
+        if h.value:
+            lib.t2s2_destroy(h)
+    # the other schemes ignore btilde and bbar
+    rc, h = _create(_good_cfg(scheme=1, btilde=(9.0, 9.0, 9.0), bbar=(9.0, 9.0, 9.0)),
+                    _axis(20), _axis(20))
     assert rc == t2s2.OK
     lib.t2s2_destroy(h)
 
@@ -177,7 +188,10 @@ def test_stability_map_argument_checks_without_device():
     fam.model, fam.eta, fam.A, fam.nk, fam.full_kx, fam.squarings = 3, 0.1, 0.5, 9, 1, 30
     fam.btilde[0], fam.btilde[1], fam.btilde[2] = 0.25, math.inf, 0.25
     assert lib.t2s2_stability_map(ctypes.byref(fam), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
-    fam.btilde[1] = 0.5   # valid: fails only on the NULL arrays
+    fam.btilde[1] = 0.5
+    fam.bbar[0], fam.bbar[1], fam.bbar[2] = 0.25, math.nan, 0.25
+    assert lib.t2s2_stability_map(ctypes.byref(fam), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
+    fam.bbar[1] = 0.5   # valid: fails only on the NULL arrays
     assert lib.t2s2_stability_map(ctypes.byref(fam), None, None, 4, None, None) == t2s2.ERR_INVALID_ARG
     assert lib.t2s2_stability_map(ctypes.byref(fam), None, None, 0, None, None) == t2s2.OK
 

@@ -28,6 +28,10 @@ CASES = [
     ("paper", dict(eta=0.1, u=(0.2, 0.2), B2bar=0.25, B2tilde=0.5), False),
     ("family", dict(eta=0.1, u=(0.2, 0.2), A=0.5, btilde=(0.25, 0.5, 0.25)), True),
     ("family", dict(eta=0.05, u=(0.05, -0.1), A=0.3, btilde=(0.15, 0.5, 0.35)), True),
+    ("family", dict(eta=0.1, u=(0.2, 0.2), A=0.5, btilde=(0.0, 1.0, 0.0),
+                    bbar=(0.25, 0.5, 0.25)), True),
+    ("family", dict(eta=0.05, u=(0.05, -0.1), A=1.0, btilde=(0.5, 0.5, 0.0),
+                    bbar=(0.5, 0.5, 0.0)), True),
 ]
 
 
@@ -39,7 +43,8 @@ def test_stability_map_matches_oracle(model, kw, full):
     omegas = np.concatenate([[0.46, 4.6], rng.uniform(0.05, 8.0, 10)])
     rs = np.concatenate([[0.9, 0.9], rng.uniform(0.05, 1.5, 10)])
     gkw = dict(eta=kw["eta"], u=kw["u"], A=kw.get("A", 0.5), b2bar=kw.get("B2bar", 0.5),
-               b2tilde=kw.get("B2tilde", 0.0), btilde=kw.get("btilde", (0.0, 1.0, 0.0)))
+               b2tilde=kw.get("B2tilde", 0.0), btilde=kw.get("btilde", (0.0, 1.0, 0.0)),
+               bbar=kw.get("bbar", (0.5, 0.0, 0.5)))
     print(f"[gpu] stability map {model} {kw}", flush=True)
     got = t2s2.stability_map(model, omegas, rs, nk=9, full_kx=full, squarings=30, **gkw)
     got = got.cpu().numpy()
