@@ -264,7 +264,10 @@ size_t t2s2_adjoint_state_bytes(const t2s2_ctx* ctx);
 size_t t2s2_adjoint_scratch_bytes(const t2s2_ctx* ctx);
 
 /* Attach the adjoint scratch (device, 256-byte aligned).  Returns
- * T2S2_ERR_UNSUPPORTED for forced flows and for T2S2_FDLBM2.  Plans the
+ * T2S2_ERR_UNSUPPORTED for forced flows, for T2S2_FDLBM2 and the family,
+ * for the stochastically rounded storage, and when one plane of the
+ * adjoint's buffers (ny * pitch elements of its arithmetic type) is not
+ * under 4 GiB (16-bit storage above about 1.07 G nodes).  Plans the
  * reverse march from the device's compute units and the kernels' occupancy
  * (blocks of four waves, or eight on small meshes; the environment variable
  * T2S2_ADJ_ROWS=4 or 8, read here, forces the shape); launches nothing. */

@@ -313,6 +313,11 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
   // A periodic grid (no walled axis) compiles without the wall paths.
   const bool per_x = !kWalls || a.per_x, per_y = !kWalls || a.per_y;
   const long long plane = a.plane;
+  // Plane strides in bytes; every plane of the Real and Store buffers is
+  // under 4 GiB (checked when the adjoint is bound), so in-plane byte
+  // offsets fit 32 bits.
+  const unsigned long long pbr = static_cast<unsigned long long>(plane) * sizeof(Real);
+  const unsigned long long pbs = static_cast<unsigned long long>(plane) * sizeof(Store);
   const Real* S = static_cast<const Real*>(a.S);
   const Real* WX = wtab_x<Real>(a);
   const Real* WY = wtab_y<Real>(a);
@@ -418,20 +423,46 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
               wys[sc][k] = rok ? ywt(yi, sc, k) : Real(0);
             }
           }
-          const Real* mr = frame_row(r) ? muf : mcol;
+          const unsigned rb = static_cast<unsigned>(roff) * static_cast<unsigned>(sizeof(Real));
+          if constexpr (!kWalls) {
+            // No frame: mu is lam everywhere, at a wave-uniform base, so the
+            // loads walk the planes from a scalar base with 32-bit row
+            // offsets (no 64-bit vector address arithmetic).
+            unsigned tb[2][kTaps];
 #pragma unroll
-          for (int q = 1; q < kQ; ++q) {
-            mvx[q] = ex_of(q) != 0 ? mr[q * plane + roff] : Real(0);
-            if (ey_of(q) != 0) {
-              const int s = ey_of(q) > 0 ? 0 : 1;
+            for (int sc = 0; sc < 2; ++sc) {
 #pragma unroll
-              for (int k = 0; k < kTaps; ++k) {
-                const int ys = ysrc[s][k];
-                myt[q][k] = (frame_row(ys) ? muf : mcol)[q * plane + static_cast<long long>(ys) * a.pitch + c];
+              for (int k = 0; k < kTaps; ++k)
+                tb[sc][k] = static_cast<unsigned>(static_cast<long long>(ysrc[sc][k]) * a.pitch + c) *
+                            static_cast<unsigned>(sizeof(Real));
+            }
+            GlobalBytes b = plane_base(lam);
+#pragma unroll
+            for (int q = 1; q < kQ; ++q) {
+              b = next_plane(b, pbr);
+              mvx[q] = ex_of(q) != 0 ? load_at<Real>(b, rb) : Real(0);
+              if (ey_of(q) != 0) {
+                const int s = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+                for (int k = 0; k < kTaps; ++k) myt[q][k] = load_at<Real>(b, tb[s][k]);
+              }
+            }
+          } else {
+            const Real* mr = frame_row(r) ? muf : mcol;
+#pragma unroll
+            for (int q = 1; q < kQ; ++q) {
+              mvx[q] = ex_of(q) != 0 ? mr[q * plane + roff] : Real(0);
+              if (ey_of(q) != 0) {
+                const int s = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+                for (int k = 0; k < kTaps; ++k) {
+                  const int ys = ysrc[s][k];
+                  myt[q][k] = (frame_row(ys) ? muf : mcol)[q * plane + static_cast<long long>(ys) * a.pitch + c];
+                }
               }
             }
           }
-          load9(S, plane, roff, sv);
+          load_planes(S, pbr, rb, sv);
           Real lr[kQ];
           lr[0] = Real(0);
 #pragma unroll
@@ -521,10 +552,18 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
           // This row's state and mu, loaded before the ring taps so their
           // latency overlaps them.
           const long long ooff = static_cast<long long>(o) * a.pitch + c;
+          const unsigned ob = static_cast<unsigned>(ooff) * static_cast<unsigned>(sizeof(Real));
           Real v[kQ], lq[kQ];
+          {
+            Store gs[kQ];
+            load_planes(g, pbs, static_cast<unsigned>(ooff) * static_cast<unsigned>(sizeof(Store)), gs);
 #pragma unroll
-          for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(g[q * plane + ooff]);
-          load9(frame_row(o) ? muf : mcol, plane, ooff, lq);
+            for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(gs[q]);
+          }
+          if constexpr (!kWalls)
+            load_planes(lam, pbr, ob, lq);
+          else
+            load9(frame_row(o) ? muf : mcol, plane, ooff, lq);
           const Real* cen = ring + (o & (kSlots - 1)) * kQ * kLanes + lane;
           // y weights of the taps (zero where the source row is outside a
           // walled axis; the ring holds zero off the interior).
@@ -573,11 +612,11 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
 #pragma unroll
           for (int q = 0; q < kQ; ++q) {
             out[q] += static_cast<Real>(a.cPg) * lp[q] + static_cast<Real>(a.cQg) * lq[q];
-            if (lane_o) lam_out[q * plane + ooff] = out[q];
             const Real neq = v[q] - feq[q];
             dp += lp[q] * neq;
             dq += lq[q] * neq;
           }
+          if (lane_o) store_planes<false>(lam_out, pbr, ob, out);
           if (lane_o) dw += a.dcPg * static_cast<double>(dp) + a.dcQg * static_cast<double>(dq);
         }
       }

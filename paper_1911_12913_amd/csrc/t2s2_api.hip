@@ -784,6 +784,11 @@ int t2s2_bind_adjoint(t2s2_ctx* c, void* scratch) {
     return fail(T2S2_ERR_UNSUPPORTED, "the adjoint covers the storage forms rounded to nearest");
   if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255))
     return fail(T2S2_ERR_INVALID_ARG, "scratch must be a 256-byte aligned device pointer");
+  // The adjoint kernels address a plane of its arithmetic-type buffers
+  // (twice the storage's bytes for the 16-bit forms) with 32-bit byte offsets.
+  if (static_cast<long long>(c->sp.plane) * static_cast<long long>(adjoint_real_bytes(c->cfg.storage)) >=
+      (1LL << 32))
+    return fail(T2S2_ERR_UNSUPPORTED, "one plane of the adjoint's buffers must be under 4 GiB");
   AdjParams& a = c->adj;
   a.nx = c->nx;
   a.ny = c->ny;

@@ -149,6 +149,79 @@ __device__ inline void round_node_sr(const float v[kQ], unsigned pos, S out[kQ])
   }
 }
 
+// The nine planes of a row of a [9][ny][pitch] buffer, loaded or stored at
+// a 32-bit byte offset (the same for every plane) in the global
+// instructions' scalar-base form: a 64-bit plane base in SGPRs plus the
+// 32-bit offset in a VGPR.  The base walks from plane to plane in the
+// global address space and is made opaque to the optimiser at each step
+// (the asm emits nothing); otherwise the optimiser folds the plane offsets
+// into one 64-bit vector address addition per plane, or keeps nine bases
+// live in SGPRs.  Elements move as their bits.  base must be wave-uniform.
+template <int N>
+struct BitsOf;
+template <>
+struct BitsOf<2> {
+  using T = unsigned short;
+};
+template <>
+struct BitsOf<4> {
+  using T = unsigned int;
+};
+template <>
+struct BitsOf<8> {
+  using T = unsigned long long;
+};
+template <typename T>
+__device__ inline void load_planes(const T* base, unsigned long long plane_bytes, unsigned boff,
+                                   T (&out)[kQ]) {
+  using B = typename BitsOf<sizeof(T)>::T;
+  auto b = (const __attribute__((address_space(1))) char*)(base);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    asm volatile("" : "+s"(b));
+    out[q] = __builtin_bit_cast(T, *(const __attribute__((address_space(1))) B*)(b + boff));
+    b += plane_bytes;
+  }
+}
+// The same walk for loads at several offsets per plane: plane_base makes
+// the (wave-uniform) base opaque, next_plane steps it by one plane, and
+// load_at reads one element at a 32-bit byte offset from it.
+using GlobalBytes = const __attribute__((address_space(1))) char*;
+template <typename T>
+__device__ inline GlobalBytes plane_base(const T* base) {
+  auto b = (GlobalBytes)(base);
+  asm volatile("" : "+s"(b));
+  return b;
+}
+__device__ inline GlobalBytes next_plane(GlobalBytes b, unsigned long long plane_bytes) {
+  b += plane_bytes;
+  asm volatile("" : "+s"(b));
+  return b;
+}
+template <typename T>
+__device__ inline T load_at(GlobalBytes b, unsigned off) {
+  using B = typename BitsOf<sizeof(T)>::T;
+  return __builtin_bit_cast(T, *(const __attribute__((address_space(1))) B*)(b + off));
+}
+
+// kNonTemporal: streaming stores, for data the launch does not read again.
+template <bool kNonTemporal, typename T>
+__device__ inline void store_planes(T* base, unsigned long long plane_bytes, unsigned boff,
+                                    const T (&v)[kQ]) {
+  using B = typename BitsOf<sizeof(T)>::T;
+  auto b = (__attribute__((address_space(1))) char*)(base);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    asm volatile("" : "+s"(b));
+    auto p = (__attribute__((address_space(1))) B*)(b + boff);
+    if constexpr (kNonTemporal)
+      __builtin_nontemporal_store(__builtin_bit_cast(B, v[q]), p);
+    else
+      *p = __builtin_bit_cast(B, v[q]);
+    b += plane_bytes;
+  }
+}
+
 // Value of the neighbouring lane l-1 (from_below) or l+1 (from_above) of a
 // wave64, through DPP wave shifts (two 32-bit moves for a double).  Every
 // lane of the wave must hold a defined value.  bound_ctrl makes the edge

@@ -58,78 +58,26 @@ __device__ inline T* at_byte(T* base, unsigned boff) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
 }
 
-// The nine planes of a state row, loaded or stored at a 32-bit byte offset
-// (the same for every plane) in the global instructions' scalar-base form:
-// a 64-bit plane base in SGPRs plus the 32-bit offset in a VGPR.  The base
-// walks from plane to plane in the global address space and is made opaque
-// to the optimiser at each step (the asm emits nothing); otherwise the
-// optimiser folds the plane offsets into one 64-bit vector address addition
-// per plane, or keeps nine bases live in SGPRs.  Elements move as their
-// bits.
-template <int N>
-struct BitsOf;
-template <>
-struct BitsOf<2> {
-  using T = unsigned short;
-};
-template <>
-struct BitsOf<4> {
-  using T = unsigned int;
-};
-template <>
-struct BitsOf<8> {
-  using T = unsigned long long;
-};
-template <typename T>
-__device__ inline void load_planes(const T* base, unsigned long long plane_bytes, unsigned boff,
-                                   T (&out)[kQ]) {
-  using B = typename BitsOf<sizeof(T)>::T;
-  auto b = (const __attribute__((address_space(1))) char*)(base);
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    asm volatile("" : "+s"(b));
-    out[q] = __builtin_bit_cast(T, *(const __attribute__((address_space(1))) B*)(b + boff));
-    b += plane_bytes;
-  }
-}
-template <typename T>
-__device__ inline void store_planes(T* base, unsigned long long plane_bytes, unsigned boff,
-                                    const T (&v)[kQ]) {
-  using B = typename BitsOf<sizeof(T)>::T;
-  auto b = (__attribute__((address_space(1))) char*)(base);
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    asm volatile("" : "+s"(b));
-    auto p = (__attribute__((address_space(1))) B*)(b + boff);
-    // FP64 rows (448 bytes per wave) go out as non-temporal (streaming)
-    // stores: the state is not read again in this launch, and they reach HBM
-    // faster than write-back stores.  The narrower FP32 and 16-bit rows (224
-    // and 112 bytes, not line-aligned) merge better in L2 and use ordinary
-    // stores (measured: FP32 5% faster so).
-    if constexpr (std::is_same<T, double>::value)
-      __builtin_nontemporal_store(__builtin_bit_cast(B, v[q]), p);
-    else
-      *p = __builtin_bit_cast(B, v[q]);
-    b += plane_bytes;
-  }
-}
-
 // The nine new values of one interior node at byte offset boff of each
 // plane: rounded to nearest even, or, for the stochastic forms, by
-// round_node_sr with the node's offset as its position.
+// round_node_sr with the node's offset as its position.  FP64 rows (448
+// bytes per wave) go out as non-temporal (streaming) stores: the state is
+// not read again in this launch, and they reach HBM faster than write-back
+// stores.  The narrower FP32 and 16-bit rows (224 and 112 bytes, not
+// line-aligned) merge better in L2 and use ordinary stores (measured: FP32
+// 5% faster so).
 template <typename Store>
 __device__ inline void store_node(Store* dst, long long plane, unsigned boff,
                                   const typename Cvt<Store>::R (&out)[kQ]) {
+  constexpr bool kNt = std::is_same<Store, double>::value;
+  Store r[kQ];
   if constexpr (kStochastic<Store>) {
-    Store r[kQ];
     round_node_sr(out, boff, r);
-    store_planes(dst, plane * sizeof(Store), boff, r);
   } else {
-    Store r[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) r[q] = Cvt<Store>::st(out[q]);
-    store_planes(dst, plane * sizeof(Store), boff, r);
   }
+  store_planes<kNt>(dst, plane * sizeof(Store), boff, r);
 }
 
 // Row index brought into [0, n) by whole periods; the rows a piece touches
