@@ -303,12 +303,15 @@ def test_velocity_error_eq36_and_residual():
 
 
 @pytest.mark.parametrize("storage,tol", [("f32", 3e-5), ("f16", 5e-2), ("bf16", 0.6),
-                                         ("f16sr", 5e-2), ("bf16sr", 0.6)])
+                                         ("f16sr", 2e-3), ("bf16sr", 2e-2)])
 def test_reduced_precision_error_vs_oracle(storage, tol):
     """Deviation storage in FP32 / FP16 / BF16 with FP32 arithmetic and FP64
     moment sums: velocity error against the FP64 oracle, reported and bounded.
-    BF16's 8-bit significand cannot resolve this low-Mach flow's density
-    deviation (|rho - 1| ~ 1e-4 against |g| ~ 3e-3), hence its loose bound."""
+    Rounded to nearest, the 16-bit forms stagnate where a step changes a
+    value by less than half a unit in its last place (BF16 0.36, FP16 1.7e-2
+    here, hence their loose bounds); rounded stochastically they keep those
+    increments on average (measured 4.5e-3 and 5.7e-4; the bounds are about
+    four times that)."""
     case = W.tgv_case(64, 64, u0=0.01, nu=0.01, cfl=0.5, eta=0.01)
     phi0 = oracle.init(case)
     ref = oracle.run(case, phi0, 400)
