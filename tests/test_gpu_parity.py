@@ -562,6 +562,23 @@ def test_family_bbar_forced_channel_matches_oracle(k):
     _compare(case, g, d, u, v, ref)
 
 
+@pytest.mark.parametrize("storage,tol", [("f16", 5e-2), ("bf16", 0.6)])
+def test_family_bbar_16bit_storage_error_vs_oracle(storage, tol):
+    """A member with collision weights on 16-bit deviation storage (rounded to
+    nearest): velocity error against the FP64 oracle, reported and bounded as
+    for the plain step (which stagnates in these forms, see
+    test_reduced_precision_error_vs_oracle)."""
+    case = W.tgv_case(64, 64, u0=0.01, nu=0.01, cfl=0.5, eta=0.01)
+    phi0 = oracle.init(case)
+    A, bt, bb = FAMILY_BBAR[0]
+    ref = oracle.run(case, phi0, 400, scheme=3, btilde=bt, A=A, bbar=bb)
+    _, g, d, u, v = _gpu_run(case, phi0, 400, storage=storage, scheme=3, btilde=bt, A=A, bbar=bb)
+    _, ur, vr = oracle.moments(case, ref)
+    err = _rel(np.stack([u, v]), np.stack([ur, vr]))
+    print(f"    {storage} family with bbar: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
+    assert np.isfinite(err) and err <= tol
+
+
 def test_family_bbar_fp32_error_vs_oracle():
     """A member with collision weights, FP32 deviation storage: velocity
     error against the FP64 oracle, reported and bounded."""
