@@ -207,28 +207,31 @@ constexpr int kMinWaves =
     sizeof(typename Cvt<Store>::R) == 8
         ? ((kScheme == 1 || (kScheme == 2 && !kWalls)) ? 2 : 1)
         : (kScheme >= 3 ? 2
-                        : ((kScheme == 2 || kForce || kBf16Bits<Store> || kStochastic<Store> ||
-                            (kWalls && !std::is_same<Store, float>::value))
+                        : (((kScheme == 2 && (kWalls || std::is_same<Store, float>::value)) ||
+                            kForce || kBf16Bits<Store> ||
+                            kStochastic<Store> || (kWalls && !std::is_same<Store, float>::value))
                                ? 3
                                : 4));
 
-// T2S2-FDLBM2 in FP64 on a periodic mesh forms each row's f^n again, in the
-// wave that needs it, from the row reloaded from cache, instead of keeping
-// it in the first LDS ring: the ring then admits two blocks per CU (FP64
-// 792 -> 653 us per step at 4096^2).  The FP32-arithmetic forms, bound by
-// their vector instructions, keep the ring (the recompute made FP32 15%
-// slower).
+// T2S2-FDLBM2 on a periodic mesh keeps each row's f^n in the registers of
+// the wave that loaded the row, instead of in the first LDS ring: the
+// waves take the phase-2 rows in the order that makes each one's phase-2
+// row a row it loaded (in this iteration for waves 0 and 1, in the previous
+// one for waves 2 and 3), and the ring holds Q alone.  At 4096^2: FP64
+// 643 -> 503 us per step (two blocks per CU, where forming f^n again from
+// a reload of the row fetched the rows twice from HBM), BF16 261 -> 232
+// us; FP32 storage keeps the ring (365 against 374 us).  Walled meshes keep
+// f^n in the ring: eq 3.10 reads it at wall nodes that another wave loaded.
 template <typename Store, bool kWalls, int kScheme>
-constexpr bool kReloadFnOf =
-    kScheme == 2 && !kWalls && sizeof(typename Cvt<Store>::R) == 8;
+constexpr bool kFnRegsOf = kScheme == 2 && !kWalls && !std::is_same<Store, float>::value;
 
 // Planes of the first LDS ring: P for T2S2-FDLBM1 (and T1S2); for
 // T2S2-FDLBM2, Q = f~^+ (the field the prediction advects) and, for the
-// eight moving directions, the physical f^n (not with kReloadFnOf); for the
+// eight moving directions, the physical f^n (not with kFnRegsOf); for the
 // family, P, Q and the eight moving directions of f^n.
-template <int kScheme, bool kReload>
+template <int kScheme, bool kFnRegs>
 constexpr int kPPlanes =
-    kScheme == 1 ? kQ : (kScheme == 2 ? (kReload ? kQ : 2 * kQ - 1) : 3 * kQ - 1);
+    kScheme == 1 ? kQ : (kScheme == 2 ? (kFnRegs ? kQ : 2 * kQ - 1) : 3 * kQ - 1);
 
 // The fused step, templated on the storage type, the presence of a body
 // force, of walls, on the scheme, and on kSaveS (the discrete adjoint's
@@ -255,8 +258,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
     StepParams p) {
   using Real = typename Cvt<Store>::R;
   // T2S2-FDLBM2, FP64, periodic: f^n of the phase-2 row from a reload.
-  constexpr bool kReloadFn = kReloadFnOf<Store, kWalls, kScheme>;
-  constexpr int kNP = kPPlanes<kScheme, kReloadFn>;
+  constexpr bool kFnRegs = kFnRegsOf<Store, kWalls, kScheme>;
+  constexpr int kNP = kPPlanes<kScheme, kFnRegs>;
   constexpr int kSB = strips_per_block(kStorageOf<Store>, kScheme);
   constexpr int kThreads = step_threads(kStorageOf<Store>, kScheme);
   constexpr int kSizeP = kRing * kNP * kLanes, kSizeR = kRing * (kQ - 1) * kLanes;
@@ -341,8 +344,10 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
     Real qA[kQ], qB[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) qA[q] = qB[q] = Real(0);
-    // The family's V = B-1 dt Omega(f*) of this wave's phase-2 rows of this
-    // and of the previous iteration (kScheme 4 only).
+    // A value each wave forms for its own phase-2 rows, of this and of the
+    // previous iteration: the family's V = B-1 dt Omega(f*) (kScheme 4,
+    // formed in phase 2 for phase 3), or f^n (kFnRegs, formed in phase 1
+    // for phase 2).
     Real vA[kQ], vB[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) vA[q] = vB[q] = Real(0);
@@ -377,12 +382,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
       const int p0 = y0 - kHalo + kRowsPerIter * it;
 
       // ---- phase 1: P (to LDS) and Q (registers) of row p0 + t; for
-      // T2S2-FDLBM2 Q and f^n to LDS (P's coefficients then give f^n).
-      // With kReloadFn the row of phase 2 is loaded again here (a cache hit:
-      // the block loaded it at most one iteration ago), so that its f^n can
-      // be formed there.
-      Store gn[kQ];
-      if constexpr (kReloadFn) load_row(p0 - 2 + t, gn);
+      // T2S2-FDLBM2 Q and f^n to LDS (P's coefficients then give f^n), or
+      // f^n to registers (kFnRegs).
       {
         const int pr = p0 + t;
         Real g[kQ];
@@ -418,7 +419,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
             Qq += static_cast<Real>(p.cQF) * Fq;
           }
           slotP[q * kLanes + lane] = kScheme == 2 ? Qq : Pq;
-          if (kScheme == 2 && !kReloadFn && q > 0) slotP[(kQ + q - 1) * kLanes + lane] = Pq;
+          if (kScheme == 2 && !kFnRegs && q > 0) slotP[(kQ + q - 1) * kLanes + lane] = Pq;
+          if constexpr (kFnRegs) vnew[q] = Pq;
           if (kFamily) {
             slotP[(kQ + q) * kLanes + lane] = Qq;
             if (q > 0) {
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
       // take neighbouring lanes' centre values); only interior lanes 2..61
       // store.
       {
-        const int r = p0 - 2 + (gen_bbar ? (t + 2) % kRowsPerIter : t);
+        const int r = p0 - 2 + (gen_bbar || kFnRegs ? (t + 2) % kRowsPerIter : t);
         const bool row_ok =
             r >= y0 - 2 && r < y1 + 2 && (p.per_y || (r >= 1 && r <= ny - 2));
         if (row_ok) {
@@ -530,41 +532,22 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
             predict(kQ, Real(1), k.cU, k.kU, p.cUF, p.half_dt, S2, R2, rho2, ux2, uy2, false,
                     S2);
           }
-          // f^n of this node from the reloaded row (kReloadFn), with the
-          // expressions of phase 1.
+          // f^n of this node (kFnRegs): formed in phase 1 of this iteration
+          // by waves 0 and 1, of the previous one by waves 2 and 3.
           Real fn[kQ];
 #pragma unroll
           for (int q = 0; q < kQ; ++q) fn[q] = Real(0);
-          if constexpr (kReloadFn) {
-            Real g2[kQ];
+          if constexpr (kFnRegs) {
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) g2[q] = Cvt<Store>::ld(gn[q]);
-            double s2, jx2, jy2;
-            moment_sums(g2, s2, jx2, jy2);
-            Real rho0, ux0, uy0;
-            velocity(s2, jx2, jy2, rho0, ux0, uy0);
-            if (kForce) {
-              ux0 += static_cast<Real>(p.half_dt * p.Fx);
-              uy0 += static_cast<Real>(p.half_dt * p.Fy);
-            }
-            const Real d0 = static_cast<Real>(s2);
-            Real X0[kQ];
-            eq_brackets(ux0, uy0, X0);
-#pragma unroll
-            for (int q = 1; q < kQ; ++q) {
-              const Real E = d0 + rho0 * X0[q];
-              Real Pq = k.cPg * g2[q] + k.kP[wclass(q)] * E;
-              if (kForce) Pq += static_cast<Real>(p.cPF) * force_term(q, p, ux0, uy0, E);
-              fn[q] = Pq;
-            }
+            for (int q = 1; q < kQ; ++q) fn[q] = t < 2 ? vnew[q] : vold[q];
           }
           // T, the field whose gradient the full step takes: R (scheme 1),
           // f^n + R (scheme 2, halved in phase 3), b0 f^n + b1 R + b2 R2
           // (scheme 3); f^n of (row, ln) from the ring (from fn with
-          // kReloadFn, where (row, ln) is always this node).
+          // kFnRegs, where (row, ln) is always this node).
           auto t_of = [&](int q, int row, int ln, Real r1, Real r2) {
             const Real* slot = ringP + (row & (kRing - 1)) * kNP * kLanes + ln;
-            if (kScheme == 2) return r1 + (kReloadFn ? fn[q] : slot[(kQ + q - 1) * kLanes]);
+            if (kScheme == 2) return r1 + (kFnRegs ? fn[q] : slot[(kQ + q - 1) * kLanes]);
             if (kFamily)
               return k.b[0] * slot[(2 * kQ + q - 1) * kLanes] + k.b[1] * r1 + k.b[2] * r2;
             return r1;

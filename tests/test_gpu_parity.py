@@ -400,10 +400,10 @@ def test_fdlbm2_periodic_matches_oracle():
 
 
 def test_fdlbm2_periodic_forced_and_tiled_matches_oracle(monkeypatch):
-    """T2S2-FDLBM2 on a periodic mesh forms f^n of each node again from its
-    row (no f^n ring): the periodic 150x70 Taylor-Green with a uniform body
-    force, 100 steps, against the oracle, bitwise the same state for three
-    block counts."""
+    """T2S2-FDLBM2 on a periodic mesh keeps f^n of each row in the registers
+    of the wave that loaded it (no f^n ring): the periodic 150x70
+    Taylor-Green with a uniform body force, 100 steps, against the oracle,
+    bitwise the same state for three block counts."""
     case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.5, eta=0.05)
     case.force = np.array([2e-4, -1e-4])
     phi0 = oracle.init(case) + W.random_state((9, 70, 150), 1e-5, 8)
