@@ -288,12 +288,12 @@ __global__ __launch_bounds__(256) void adj_out_walls(AdjParams a, const Store* n
 // The d/d omega partials sum over the nodes each lane outputs, once each.
 // Waves per SIMD that the registers of a march variant are budgeted for.
 // The wall paths hold it at two in FP64 and three in FP32; a periodic grid
-// compiles without them, so its FP64 four-row blocks fit three per CU and
-// its FP32 ones four (whole blocks of eight waves: two per SIMD each).
+// compiles without them but holds the next phase's loads in registers, so
+// its FP64 blocks fit two per CU and its FP32 four-row ones four.
 template <typename Store, int kRows, bool kWalls>
 constexpr int adj_waves_per_simd() {
   constexpr bool f32 = sizeof(typename Cvt<Store>::R) == 4;
-  return kWalls ? (f32 && kRows == 4 ? 3 : 2) : (f32 ? 4 : (kRows == 4 ? 3 : 2));
+  return kWalls ? (f32 && kRows == 4 ? 3 : 2) : (f32 ? 4 : 2);
 }
 
 template <typename Store, int kRows, bool kWalls>
@@ -390,8 +390,66 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
     __syncthreads();  // ring zero-fill / previous piece complete
 
     const int niter = (y1 - y0 + 3 + kRows) / kRows;
+    // Periodic grids: each phase's loads are issued one phase ahead of
+    // their use, into registers -- phase A's during phase B of the previous
+    // iteration, phase B's during phase A -- so their latency overlaps the
+    // other phase's arithmetic instead of stalling the wave at every phase
+    // (the rows wrap, so every load is in the grid, also those of rows past
+    // the piece, which go unused).  Without a frame, mu is lam everywhere,
+    // at a wave-uniform base, so the loads walk the planes from a scalar
+    // base with 32-bit row offsets.
+    // Phase A of row r: lam of populations 1..8 at (c, r) (the centre tap
+    // of the y-moving ones too), their other three y taps, S at (c, r) and
+    // the row's y weights.
+    Real a_lc[kQ], a_yt[kQ][kTaps], a_sv[kQ], a_wy[2][kTaps];
+    // Phase B of row o: the state and lam at (c, o), the y weights at o.
+    Store b_gs[kQ];
+    Real b_lq[kQ], b_wy[2][kTaps];
+    auto issue_a = [&](int r0) {
+      const int r = wrap(r0, ny);
+      const unsigned rb = static_cast<unsigned>(static_cast<long long>(r) * a.pitch + c) *
+                          static_cast<unsigned>(sizeof(Real));
+      unsigned tb[2][kTaps];
+#pragma unroll
+      for (int sc = 0; sc < 2; ++sc) {
+#pragma unroll
+        for (int k = 0; k < kTaps; ++k) {
+          const int yi = along(r, -tap_offset(sc, k), ny, true);
+          tb[sc][k] = static_cast<unsigned>(static_cast<long long>(yi) * a.pitch + c) *
+                      static_cast<unsigned>(sizeof(Real));
+          a_wy[sc][k] = ywt(yi, sc, k);
+        }
+      }
+      GlobalBytes b = plane_base(lam);
+#pragma unroll
+      for (int q = 1; q < kQ; ++q) {
+        b = next_plane(b, pbr);
+        a_lc[q] = load_at<Real>(b, rb);
+        if (ey_of(q) != 0) {
+          const int sq = ey_of(q) > 0 ? 0 : 1;
+#pragma unroll
+          for (int k = 0; k < kTaps; ++k)
+            if (tap_offset(sq, k) != 0) a_yt[q][k] = load_at<Real>(b, tb[sq][k]);
+        }
+      }
+      load_planes(S, pbr, rb, a_sv);
+    };
+    auto issue_b = [&](int o0) {
+      const int o = wrap(o0, ny);
+      const unsigned ooff = static_cast<unsigned>(static_cast<long long>(o) * a.pitch + c);
+      load_planes(g, pbs, ooff * static_cast<unsigned>(sizeof(Store)), b_gs);
+      load_planes(lam, pbr, ooff * static_cast<unsigned>(sizeof(Real)), b_lq);
+#pragma unroll
+      for (int sc = 0; sc < 2; ++sc) {
+#pragma unroll
+        for (int k = 0; k < kTaps; ++k)
+          b_wy[sc][k] = ywt(along(o, -tap_offset(sc, k), ny, true), sc, k);
+      }
+    };
+    if constexpr (!kWalls) issue_a(y0 - 2 + t);
     for (int it = 0; it < niter; ++it) {
       const int p0 = y0 - 2 + kRows * it;
+      if constexpr (!kWalls) issue_b(p0 - 2 + t);
 
       // ---- phase A: lamS of row r
       {
@@ -412,42 +470,37 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
           // weight 0, where the source row is not interior) and S at (c, r).
           // 20% faster at 513^2, 30% at 4096^2, the same values.
           Real mvx[kQ], myt[kQ][kTaps], wys[2][kTaps], sv[kQ];
-          int ysrc[2][kTaps];
-#pragma unroll
-          for (int sc = 0; sc < 2; ++sc) {
-#pragma unroll
-            for (int k = 0; k < kTaps; ++k) {
-              const int yi = along(r, -tap_offset(sc, k), ny, per_y);
-              const bool rok = yi >= 0 && (per_y || (yi >= 1 && yi <= ny - 2));
-              ysrc[sc][k] = rok ? yi : r;
-              wys[sc][k] = rok ? ywt(yi, sc, k) : Real(0);
-            }
-          }
-          const unsigned rb = static_cast<unsigned>(roff) * static_cast<unsigned>(sizeof(Real));
           if constexpr (!kWalls) {
-            // No frame: mu is lam everywhere, at a wave-uniform base, so the
-            // loads walk the planes from a scalar base with 32-bit row
-            // offsets (no 64-bit vector address arithmetic).
-            unsigned tb[2][kTaps];
-#pragma unroll
-            for (int sc = 0; sc < 2; ++sc) {
-#pragma unroll
-              for (int k = 0; k < kTaps; ++k)
-                tb[sc][k] = static_cast<unsigned>(static_cast<long long>(ysrc[sc][k]) * a.pitch + c) *
-                            static_cast<unsigned>(sizeof(Real));
-            }
-            GlobalBytes b = plane_base(lam);
+            // Issued by issue_a one phase earlier.
 #pragma unroll
             for (int q = 1; q < kQ; ++q) {
-              b = next_plane(b, pbr);
-              mvx[q] = ex_of(q) != 0 ? load_at<Real>(b, rb) : Real(0);
+              mvx[q] = ex_of(q) != 0 ? a_lc[q] : Real(0);
               if (ey_of(q) != 0) {
                 const int s = ey_of(q) > 0 ? 0 : 1;
 #pragma unroll
-                for (int k = 0; k < kTaps; ++k) myt[q][k] = load_at<Real>(b, tb[s][k]);
+                for (int k = 0; k < kTaps; ++k)
+                  myt[q][k] = tap_offset(s, k) == 0 ? a_lc[q] : a_yt[q][k];
               }
             }
+#pragma unroll
+            for (int sc = 0; sc < 2; ++sc) {
+#pragma unroll
+              for (int k = 0; k < kTaps; ++k) wys[sc][k] = a_wy[sc][k];
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) sv[q] = a_sv[q];
           } else {
+            int ysrc[2][kTaps];
+#pragma unroll
+            for (int sc = 0; sc < 2; ++sc) {
+#pragma unroll
+              for (int k = 0; k < kTaps; ++k) {
+                const int yi = along(r, -tap_offset(sc, k), ny, per_y);
+                const bool rok = yi >= 0 && (per_y || (yi >= 1 && yi <= ny - 2));
+                ysrc[sc][k] = rok ? yi : r;
+                wys[sc][k] = rok ? ywt(yi, sc, k) : Real(0);
+              }
+            }
             const Real* mr = frame_row(r) ? muf : mcol;
 #pragma unroll
             for (int q = 1; q < kQ; ++q) {
@@ -461,8 +514,9 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
                 }
               }
             }
+            const unsigned rb = static_cast<unsigned>(roff) * static_cast<unsigned>(sizeof(Real));
+            load_planes(S, pbr, rb, sv);
           }
-          load_planes(S, pbr, rb, sv);
           Real lr[kQ];
           lr[0] = Real(0);
 #pragma unroll
@@ -542,6 +596,7 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
 #pragma unroll
         for (int q = 0; q < kQ; ++q) slot[q * kLanes + lane] = ls[q];
       }
+      if constexpr (!kWalls) issue_a(p0 + kRows + t);  // phase A of the next iteration
       __syncthreads();
 
       // ---- phase B: lam_n of row o
@@ -549,33 +604,45 @@ __global__ __launch_bounds__(kLanes * kRows, (adj_waves_per_simd<Store, kRows, k
         const int o = p0 - 2 + t;
         if (o >= y0 && o < y1) {  // uniform per wave
           const bool nin = col_int && (per_y || (o >= 1 && o <= ny - 2));
-          // This row's state and mu, loaded before the ring taps so their
-          // latency overlaps them.
+          // This row's state and mu: on walled grids loaded here, before the
+          // ring taps, so their latency overlaps them; on periodic grids
+          // issued at the start of the iteration.
           const long long ooff = static_cast<long long>(o) * a.pitch + c;
           const unsigned ob = static_cast<unsigned>(ooff) * static_cast<unsigned>(sizeof(Real));
           Real v[kQ], lq[kQ];
-          {
-            Store gs[kQ];
-            load_planes(g, pbs, static_cast<unsigned>(ooff) * static_cast<unsigned>(sizeof(Store)), gs);
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(gs[q]);
-          }
-          if constexpr (!kWalls)
-            load_planes(lam, pbr, ob, lq);
-          else
-            load9(frame_row(o) ? muf : mcol, plane, ooff, lq);
-          const Real* cen = ring + (o & (kSlots - 1)) * kQ * kLanes + lane;
           // y weights of the taps (zero where the source row is outside a
           // walled axis; the ring holds zero off the interior).
           Real wyo[2][kTaps];
+          if constexpr (!kWalls) {
+            // Issued by issue_b at the start of the iteration.
 #pragma unroll
-          for (int sc = 0; sc < 2; ++sc) {
+            for (int q = 0; q < kQ; ++q) {
+              v[q] = Cvt<Store>::ld(b_gs[q]);
+              lq[q] = b_lq[q];
+            }
 #pragma unroll
-            for (int k = 0; k < kTaps; ++k) {
-              const int yi = along(o, -tap_offset(sc, k), ny, per_y);
-              wyo[sc][k] = yi >= 0 ? ywt(yi, sc, k) : Real(0);
+            for (int sc = 0; sc < 2; ++sc) {
+#pragma unroll
+              for (int k = 0; k < kTaps; ++k) wyo[sc][k] = b_wy[sc][k];
+            }
+          } else {
+            {
+              Store gs[kQ];
+              load_planes(g, pbs, static_cast<unsigned>(ooff) * static_cast<unsigned>(sizeof(Store)), gs);
+#pragma unroll
+              for (int q = 0; q < kQ; ++q) v[q] = Cvt<Store>::ld(gs[q]);
+            }
+            load9(frame_row(o) ? muf : mcol, plane, ooff, lq);
+#pragma unroll
+            for (int sc = 0; sc < 2; ++sc) {
+#pragma unroll
+              for (int k = 0; k < kTaps; ++k) {
+                const int yi = along(o, -tap_offset(sc, k), ny, per_y);
+                wyo[sc][k] = yi >= 0 ? ywt(yi, sc, k) : Real(0);
+              }
             }
           }
+          const Real* cen = ring + (o & (kSlots - 1)) * kQ * kLanes + lane;
           Real lp[kQ];
 #pragma unroll
           for (int q = 0; q < kQ; ++q) {
