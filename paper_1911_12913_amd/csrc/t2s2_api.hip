@@ -424,6 +424,15 @@ int t2s2_create(const t2s2_config* cfg, const double* x, int nx, const double* y
   for (int s = 0; s < 4; ++s) {
     p.uw[s][0] = cfg->u_wall[s][0];
     p.uw[s][1] = cfg->u_wall[s][1];
+    // D2Q9 velocities in the paper's order (Sec. 3).
+    static const int ex[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const int ey[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const double ux = p.uw[s][0], uy = p.uw[s][1], uu = 1.5 * (ux * ux + uy * uy);
+    for (int q = 0; q < kQ; ++q) {
+      const double e = ex[q] * ux + ey[q] * uy;
+      p.xb[s][q] = e * (3.0 + 4.5 * e) - uu;
+      p.xb32[s][q] = static_cast<float>(p.xb[s][q]);
+    }
   }
 
   c->wx = stencil_weights(metric(xs, cfg->periodic_x, cfg->period_x), cfg->periodic_x, cfg->eta, dt);

@@ -367,6 +367,33 @@ __device__ inline void nee_shift(double rho, double uxf, double uyf, double uxb,
   }
 }
 
+// f^eq(rho, u_b) - f^eq(rho, u_f) of eq 3.10 for q >= 1 from the brackets
+// Xf of the fluid node's velocity (eq_brackets) and Xb of the wall's
+// (StepParams::xb): w_q rho (Xb_q - Xf_q).  out[0] is not formed.
+template <typename Real>
+__device__ inline void nee_shift_x(Real rho, const Real (&Xf)[kQ], const Real* Xb, Real out[kQ]) {
+  const Real r1 = Real(w_of(1)) * rho, r2 = Real(w_of(5)) * rho;
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) out[q] = (wclass(q) == 1 ? r1 : r2) * (Xb[q] - Xf[q]);
+}
+
+// The wall whose node (i + dx, j + dy) is extrapolated from the fluid node
+// (i, j) next to it (dx, dy in -1..1, not both 0; a corner counts as its x
+// wall): 0 for x = 0, 1 for x = nx-1, 2 for y = 0, 3 for y = ny-1.
+__host__ __device__ constexpr int wall_side_of(int dx, int dy) {
+  return dx < 0 ? 0 : (dx > 0 ? 1 : (dy < 0 ? 2 : 3));
+}
+template <typename Real>
+__device__ inline const Real* wall_brackets(const StepParams& p, int side);
+template <>
+__device__ inline const double* wall_brackets<double>(const StepParams& p, int side) {
+  return p.xb[side];
+}
+template <>
+__device__ inline const float* wall_brackets<float>(const StepParams& p, int side) {
+  return p.xb32[side];
+}
+
 __device__ inline void wall_velocity(const StepParams& p, int c, int r, double& ub,
                                      double& vb) {
   int side;

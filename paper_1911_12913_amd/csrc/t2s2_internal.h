@@ -98,6 +98,11 @@ struct StepParams {
   double half_dt, half_h;
   double Fx, Fy;
   double uw[4][2];
+  // Brackets X_q(u_b) = 3 e + 9/2 e^2 - 3/2 |u_b|^2 (e = xi_q . u_b) of each
+  // wall's velocity, for the extrapolation of eq 3.10 (sides: x = 0,
+  // x = nx-1, y = 0, y = ny-1), FP64 and FP32.
+  double xb[4][kQ];
+  float xb32[4][kQ];
   int has_force;
   // The coefficients in the arithmetic type of the kernel: cPg, cQg, cRs,
   // A, cU = cUg, and per lattice-weight class c (rest, axis, diagonal) the

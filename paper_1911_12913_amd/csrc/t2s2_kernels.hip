@@ -465,7 +465,7 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
           // gradient).
           auto predict = [&](int base, Real fac, Real cs, const Real* ke, double cf, double hf,
                              Real (&S)[kQ], Real (&R)[kQ], Real& rho, Real& ux, Real& uy,
-                             bool want_v, Real (&V)[kQ]) {
+                             Real (&X)[kQ], bool want_v, Real (&V)[kQ]) {
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
               const int pq = (base + q) * kLanes;
@@ -488,7 +488,6 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
               uy += static_cast<Real>(hf * p.Fy);
             }
             const Real d = static_cast<Real>(s);
-            Real X[kQ];
             eq_brackets(ux, uy, X);
             R[0] = Real(0);
 #pragma unroll
@@ -513,8 +512,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
               }
             }
           };
-          Real S[kQ], R[kQ], rho, ux, uy;
-          predict(0, k.A, k.cRs, k.kR, p.cRF, p.half_h, S, R, rho, ux, uy, gen_bbar, vnew);
+          Real S[kQ], R[kQ], X[kQ], rho, ux, uy;
+          predict(0, k.A, k.cRs, k.kR, p.cRF, p.half_h, S, R, rho, ux, uy, X, gen_bbar, vnew);
           if (kSaveS && lane_o && col_interior && r >= y0 && r < y1) {
             Real* sv = static_cast<Real*>(p.save_s);
             const unsigned boff =
@@ -524,12 +523,12 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
             for (int q = 0; q < kQ; ++q) *at_byte(sv + q * plane, boff) = S[q];
           }
           // The family's second prediction: f^{n+1} from Q with h = dt.
-          Real R2[kQ], rho2 = Real(1), ux2 = Real(0), uy2 = Real(0);
+          Real R2[kQ], X2[kQ], rho2 = Real(1), ux2 = Real(0), uy2 = Real(0);
 #pragma unroll
-          for (int q = 0; q < kQ; ++q) R2[q] = Real(0);
+          for (int q = 0; q < kQ; ++q) R2[q] = X2[q] = Real(0);
           if constexpr (kFamily) {
             Real S2[kQ];
-            predict(kQ, Real(1), k.cU, k.kU, p.cUF, p.half_dt, S2, R2, rho2, ux2, uy2, false,
+            predict(kQ, Real(1), k.cU, k.kU, p.cUF, p.half_dt, S2, R2, rho2, ux2, uy2, X2, false,
                     S2);
           }
           // f^n of this node (kFnRegs): formed in phase 1 of this iteration
@@ -568,16 +567,14 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, kScheme), (kMinWave
                 for (int dx = -1; dx <= 1; ++dx) {
                   if ((dx == -1 && !src_xl) || (dx == 1 && !src_xr)) continue;
                   if (dx == 0 && dy == 0) continue;
-                  double ub, vb;
-                  wall_velocity(p, c + dx, r + dy, ub, vb);
+                  // The shift from the brackets of u_f, formed above, and
+                  // of the wall's velocity.
+                  const Real* Xb = wall_brackets<Real>(p, wall_side_of(dx, dy));
                   Real sh[kQ], sh2[kQ];
-                  nee_shift(static_cast<double>(rho), static_cast<double>(ux),
-                            static_cast<double>(uy), ub, vb, sh);
+                  nee_shift_x(rho, X, Xb, sh);
 #pragma unroll
                   for (int q = 0; q < kQ; ++q) sh2[q] = Real(0);
-                  if constexpr (kFamily)
-                    nee_shift(static_cast<double>(rho2), static_cast<double>(ux2),
-                              static_cast<double>(uy2), ub, vb, sh2);
+                  if constexpr (kFamily) nee_shift_x(rho2, X2, Xb, sh2);
                   Real* slotW = dy == 1 ? topR : ringR + ((r + dy) & (kRing - 1)) * (kQ - 1) * kLanes;
 #pragma unroll
                   for (int q = 1; q < kQ; ++q)
@@ -845,11 +842,8 @@ __global__ __launch_bounds__(kTileWaves * kLanes) void tile_step_kernel(StepPara
           for (int dx = -1; dx <= 1; ++dx) {
             if ((dx == -1 && !src_xl) || (dx == 1 && !src_xr)) continue;
             if (dx == 0 && dy == 0) continue;
-            double ub, vb;
-            wall_velocity(p, c + dx, r + dy, ub, vb);
             Real sh[kQ];
-            nee_shift(static_cast<double>(rho), static_cast<double>(ux),
-                      static_cast<double>(uy), ub, vb, sh);
+            nee_shift_x(rho, X, wall_brackets<Real>(p, wall_side_of(dx, dy)), sh);
             Real* slotW = tR + (m + dy) * (kQ - 1) * kLanes;
 #pragma unroll
             for (int q = 1; q < kQ; ++q) slotW[(q - 1) * kLanes + lane + dx] = R[q] + sh[q];
@@ -1053,6 +1047,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, 0), (kMinWaves<Stor
             moment_sums(R, s2, jx2, jy2);
             Real rho2, ux2, uy2;
             velocity(s2, jx2, jy2, rho2, ux2, uy2);
+            Real X2[kQ];
+            eq_brackets(ux2, uy2, X2);
             for (int dy = -1; dy <= 1; ++dy) {
               if ((dy == -1 && !src_yb) || (dy == 1 && !src_yt)) continue;
               for (int dx = -1; dx <= 1; ++dx) {
@@ -1061,11 +1057,8 @@ __global__ __launch_bounds__(step_threads(kStorageOf<Store>, 0), (kMinWaves<Stor
                 // A source in the strip's edge lane has its wall node outside
                 // the strip; no output of this strip reads it.
                 if (lane + dx < 0 || lane + dx >= kLanes) continue;
-                double ub, vb;
-                wall_velocity(p, c + dx, pr + dy, ub, vb);
                 Real sh[kQ];
-                nee_shift(static_cast<double>(rho2), static_cast<double>(ux2),
-                          static_cast<double>(uy2), ub, vb, sh);
+                nee_shift_x(rho2, X2, wall_brackets<Real>(p, wall_side_of(dx, dy)), sh);
                 Real* slotW = ringR + ((pr + dy) & (kRing1 - 1)) * (kQ - 1) * kLanes;
 #pragma unroll
                 for (int q = 1; q < kQ; ++q) slotW[(q - 1) * kLanes + lane + dx] = R[q] + sh[q];
