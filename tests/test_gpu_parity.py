@@ -151,6 +151,31 @@ def test_collisionless_advection():
     assert _rel(g, ref) <= TOL
 
 
+@pytest.mark.parametrize("kernel", ["march", "tile", "t1s2"])
+def test_moving_walls_on_every_side_match_oracle(kernel, monkeypatch):
+    """Each of the four walls moves with its own velocity (tangential and
+    normal parts), so the extrapolation of eq 3.10 at every wall and
+    corner takes the brackets of its own wall's velocity (corners belong to
+    the x walls): the march (forced block count), the tile kernel and the
+    single-stencil kernel (A = 0), FP64 against the oracle, 60 steps of a
+    ragged cavity."""
+    A = 0.0 if kernel == "t1s2" else 0.5
+    case = W.cavity_case(64, lid=0.1, re=400.0, cfl=0.5 if A == 0.0 else 0.8, eta=0.1,
+                         noise=1e-5, seed=4, A=A)
+    case.u_wall[:] = np.array([[0.002, 0.03], [-0.001, -0.02], [0.025, 0.003], [0.1, -0.002]])
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 60)
+    if kernel == "march":
+        monkeypatch.setenv("T2S2_BLOCKS", "16")
+    else:
+        monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+    _, g, d, u, v = _gpu_run(case, phi0, 60)
+    _compare(case, g, d, u, v, ref)
+    if kernel == "march":  # the FP32 copy of the wall brackets
+        _, g32, *_ = _gpu_run(case, phi0, 60, storage="f32")
+        assert _rel(g32, ref) <= 1e-5
+
+
 def test_rest_state_exact_zero():
     case = W.cavity_case(40, noise=0.0)
     case.u_wall[:] = 0.0
