@@ -476,6 +476,39 @@ def test_fdlbm2_fp32_error_vs_oracle():
     assert err <= 3e-5
 
 
+
+# The 16-bit forms' T2S2-FDLBM2 bounds: about four times the errors measured
+# on the two meshes below after 40 steps (BF16 2.1e-2 and 1.9e-3, FP16
+# 2.3e-3 and 1.1e-4).
+FDLBM2_16BIT_TOL = {("tgv150x70", "bf16"): 8e-2, ("tgv150x70", "f16"): 1e-2,
+                    ("cavity130x65", "bf16"): 8e-3, ("cavity130x65", "f16"): 5e-4}
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("kind", ["tgv150x70", "cavity130x65"])
+def test_fdlbm2_16bit_matches_oracle_and_tiling(kind, storage, monkeypatch):
+    """T2S2-FDLBM2 with 16-bit storage: on the periodic mesh f^n of a row
+    stays in the registers of the wave that loaded it, on the walled one in
+    the LDS ring.  Bitwise the same state for two block counts, and the
+    velocity within the form's error of the FP64 oracle after 40 steps."""
+    if kind == "tgv150x70":
+        case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.5, eta=0.05)
+        phi0 = oracle.init(case) + W.random_state((9, 70, 150), 1e-5, 9)
+    else:
+        case = _ragged_cavity(0.5)
+        phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 40, scheme=2)
+    outs = []
+    for blocks in ("8", "40"):
+        monkeypatch.setenv("T2S2_BLOCKS", blocks)
+        _, g, d, u, v = _gpu_run(case, phi0, 40, storage=storage, scheme=2)
+        outs.append(g)
+    assert np.array_equal(outs[0], outs[1])
+    _, ur, vr = oracle.moments(case, ref)
+    err = _rel(np.stack([u, v]), np.stack([ur, vr]))
+    print(f"    {storage} FDLBM2 {kind}: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
+    assert err <= FDLBM2_16BIT_TOL[kind, storage]
+
 # ------------------------- the eq 2.13 family (gradient weights btilde)
 
 FAMILY = [(0.5, (0.25, 0.5, 0.25)), (0.3, (0.15, 0.5, 0.35))]
