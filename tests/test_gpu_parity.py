@@ -133,6 +133,34 @@ def test_poiseuille_forced_narrow_periodic():
     _compare(case, g, d, u, v, ref)
 
 
+
+# Reduced forms on the forced channel: bounds about four times the errors
+# measured after 500 steps (FP32 2.9e-6; rounded to nearest BF16 0.21 and
+# FP16 8.5e-3, the stagnation of sub-ulp increments; stochastically rounded
+# BF16 3.8e-3 and FP16 5.9e-4).
+POISEUILLE_FORM_TOL = {"f32": 1.2e-5, "bf16": 0.6, "f16": 3.5e-2, "bf16sr": 1.5e-2,
+                       "f16sr": 2.5e-3}
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16", "bf16sr", "f16sr"])
+def test_poiseuille_forced_reduced_forms(storage, monkeypatch):
+    """The force-driven channel (Guo term, x periodic, y walls) in the reduced
+    storage forms: the tile kernel and the march (forced block count) give
+    bitwise the same state, and its velocity is within the form's error of
+    the FP64 oracle after 500 steps."""
+    case = W.poiseuille_case(dt_over_y1=0.9, eta=0.1)
+    phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 500)
+    monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+    _, g_tile, d, u, v = _gpu_run(case, phi0, 500, storage=storage)
+    monkeypatch.setenv("T2S2_BLOCKS", "8")
+    _, g_march, *_ = _gpu_run(case, phi0, 500, storage=storage)
+    assert np.array_equal(g_tile, g_march)
+    _, ur, vr = oracle.moments(case, ref)
+    err = _rel(np.stack([u, v]), np.stack([ur, vr]))
+    print(f"    {storage} forced channel: velocity rel L2 vs FP64 oracle {err:.3e}", flush=True)
+    assert err <= POISEUILLE_FORM_TOL[storage]
+
 @pytest.mark.parametrize("A", [0.0, 0.5, 1.0])
 def test_stage_parameter_A(A):
     """A = 0 is Guo's T1S2 (Remark I); A = 1 is a valid member of the family."""
