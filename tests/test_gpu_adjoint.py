@@ -179,6 +179,48 @@ def test_fp32_adjoint_step_matches_fp64_adjoint_step(kind):
     assert e_l < 1e-5 and e_nu < 1e-3
 
 
+
+def _round_16bit(g, storage):
+    """Deviations rounded to the values the 16-bit form stores exactly (BF16:
+    to nearest even on the FP32 bits; FP16: 2^14 g to the nearest FP16)."""
+    if storage == "bf16":
+        u = g.astype(np.float32).view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return (g * 16384.0).astype(np.float16).astype(np.float64) / 16384.0
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_adjoint_16bit_storage_is_the_fp32_adjoint(storage):
+    """On a periodic grid the adjoint step reads the state only through the
+    storage type and keeps lambda in FP32 for every reduced form, so with a
+    state that the 16-bit form holds exactly the BF16 and FP16 adjoints give
+    the FP32-storage adjoint's lambda_n and dL/dnu bit for bit (150 x 70
+    Taylor-Green, ragged strips)."""
+    case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.6, eta=0.05)
+    print(f"[gpu] 16-bit adjoint vs FP32 adjoint {storage}", flush=True)
+    g = _round_16bit(oracle.run(case, oracle.init(case) + W.random_state((9, 70, 150), 1e-5, 31),
+                                10), storage)
+    w = W.random_state(g.shape, 1.0, 32).astype(np.float32).astype(np.float64)
+    outs = {}
+    for st in (storage, "f32"):
+        ctx = t2s2.context_for_case(case, storage=st)
+        ctx.enable_adjoint()
+        ctx.init_distributions(torch.from_numpy(g))
+        state = ctx.save_state()
+        lam_w = ctx.adjoint_load(w)
+        lam_out = ctx.adjoint_buffer()
+        acc = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        ctx.adjoint_step(state, lam_w, lam_out, acc)
+        outs[st] = (ctx.adjoint_read(lam_out).cpu().numpy(), float(acc.item()),
+                    ctx.read_distributions().cpu().numpy())
+        ctx.close()
+    assert np.array_equal(outs[storage][2], g) and np.array_equal(outs["f32"][2], g)
+    print(f"    lambda_n bitwise {np.array_equal(outs[storage][0], outs['f32'][0])}, "
+          f"dL/dnu {outs[storage][1]!r} vs {outs['f32'][1]!r}", flush=True)
+    assert np.array_equal(outs[storage][0], outs["f32"][0])
+    assert outs[storage][1] == outs["f32"][1]
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_adjoint_march_block_shapes_agree(storage, monkeypatch):
     """The reverse march with blocks of four waves and of eight (forced with
