@@ -11,6 +11,10 @@ and the precision-form errors of the large cavity.
 * Lid-driven cavity 2049 x 2049 (Re 5000, CFL 0.9, eta 0.05): 20 FP64 steps
   against the oracle; after 20000 steps the relative L2 velocity error of
   the FP32, FP16 and BF16 storage forms against FP64.
+* The largest FP64 mesh a context takes (one population plane just under
+  4 GiB, 23040 x 23040): two steps against the oracle on windows around
+  sampled nodes, among them nodes past the 2 GiB and near the 4 GiB offset
+  of their plane.
 """
 import math
 import time
@@ -381,3 +385,67 @@ def test_copy_probe_is_a_bitwise_copy(dtype):
     torch.cuda.synchronize()
     assert torch.equal(src.view(torch.int8 if dt != torch.float16 else torch.int16),
                        dst.view(torch.int8 if dt != torch.float16 else torch.int16))
+
+
+# ------------------------------------------------ the largest FP64 mesh
+
+def _hashed_state(q, j, i):
+    """A seeded state defined node by node in integer arithmetic, so that the
+    device (torch) and the host (numpy) form the same values: deviations
+    (v - 500) 2^-22 with v = (73 i + 151 j + 37 q + 11 ((i j) mod 97)) mod 1001."""
+    return ((i * 73 + j * 151 + q * 37 + ((i * j) % 97) * 11) % 1001 - 500) * 2.0 ** -22
+
+
+def test_largest_fp64_plane_matches_oracle_on_windows():
+    """A periodic 23040 x 23040 FP64 mesh (unit spacing), one plane
+    23040^2 x 8 B = 4.25e9 B, just under the 4 GiB that the kernels' 32-bit
+    in-plane byte offsets address: two steps from a hashed state, then, at
+    sampled nodes (rows 0..23039, among them rows past 2 GiB = row 11651 and
+    the last rows), the GPU state against the oracle run on a 31 x 31 walled
+    window around the node.  Outputs 9 or more nodes from the window's edge
+    depend only on the window's interior, with the full mesh's weights, so
+    the 13 x 13 centre of each window must match to FP64 rounding."""
+    n = 23040
+    free, _ = torch.cuda.mem_get_info()
+    if free < 180e9:
+        pytest.skip(f"needs about 160 GB of device memory ({free / 1e9:.0f} GB free)")
+    nu, cfl, eta = 0.1, 0.5, 0.05
+    ax = np.arange(n, dtype=np.float64)
+    case = W.Case(name="largest", x=ax, y=ax, periodic_x=True, periodic_y=True,
+                  period_x=float(n), period_y=float(n), nu=nu, cfl=cfl, eta=eta)
+    _say(f"[gpu] largest FP64 plane {n}x{n}")
+    ctx = t2s2.context_for_case(case, storage="f64")
+    g = torch.empty((9, n, n), dtype=torch.float64, device="cuda:0")
+    I = torch.arange(n, dtype=torch.int64, device="cuda:0")[None, :]
+    J = torch.arange(n, dtype=torch.int64, device="cuda:0")[:, None]
+    for q in range(9):
+        g[q] = _hashed_state(q, J, I).to(torch.float64)
+    del I, J
+    ctx.init_distributions(g)
+    del g
+    torch.cuda.empty_cache()
+    ctx.step(2)
+    out = ctx.read_distributions()
+    m, lo, hi = 31, 9, 22
+    corners = [(0, 0), (11640, 5000), (11651 - 15, 20000), (n - m, n - m), (17000, n - m),
+               (n - m, 3)]
+    worst = 0.0
+    for j0, i0 in corners:
+        xw = np.arange(i0, i0 + m, dtype=np.float64)
+        yw = np.arange(j0, j0 + m, dtype=np.float64)
+        win = W.Case(name="window", x=xw, y=yw, periodic_x=False, periodic_y=False,
+                     period_x=0.0, period_y=0.0, nu=nu, cfl=cfl, eta=eta)
+        jj, ii = np.meshgrid(np.arange(j0, j0 + m), np.arange(i0, i0 + m), indexing="ij")
+        phi = np.stack([_hashed_state(q, jj, ii) for q in range(9)]).astype(np.float64)
+        ref = oracle.run(win, phi, 2)[:, lo:hi, lo:hi]
+        got = out[:, j0 + lo:j0 + hi, i0 + lo:i0 + hi].cpu().numpy()
+        e = _rel(got, ref)
+        em = float(np.abs(got - ref).max()) / float(np.abs(ref).max())
+        _say(f"    window rows {j0}..{j0 + m - 1}, columns {i0}..{i0 + m - 1}: "
+             f"rel L2 {e:.2e}, max {em:.2e}")
+        worst = max(worst, e, em)
+    del out
+    ctx.close()
+    torch.cuda.empty_cache()
+    assert worst <= 1e-12
+
