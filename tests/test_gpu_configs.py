@@ -406,6 +406,7 @@ def test_largest_fp64_plane_matches_oracle_on_windows():
     depend only on the window's interior, with the full mesh's weights, so
     the 13 x 13 centre of each window must match to FP64 rounding."""
     n = 23040
+    torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
     if free < 180e9:
         pytest.skip(f"needs about 160 GB of device memory ({free / 1e9:.0f} GB free)")
