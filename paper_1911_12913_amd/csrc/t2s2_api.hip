@@ -129,14 +129,56 @@ void plan_strips(StepParams& p, int storage) {
   p.band = p.ny;
 }
 
+// Band height of the march's split of nunits x ny unit-rows over nb blocks:
+// one block's share, so that away from the last band a block owns one unit
+// of one band.
+int band_of(long long nunits, int ny, long long nb) {
+  const long long rows = nunits * ny;
+  return static_cast<int>(std::min<long long>(ny, std::max<long long>(1, (rows + nb - 1) / nb)));
+}
+
+// Work of the busiest block under that split, in unit-rows: the rows of its
+// range plus kPieceWork for each piece the range is cut into at unit and
+// band ends (a piece refills the march's pipeline: it loads the four rows
+// above and below its range again and runs its leading and trailing
+// iterations).  The ranges and pieces are enumerated as the step kernels
+// cut them.  A last band of a few rows cuts each range that covers it into
+// one piece per unit: on a 4060^2 grid in FP64 the default 512 blocks leave
+// a last band of 7 rows and 74 pieces in the busiest range.
+constexpr long long kPieceWork = 4;  // fitted to step times at 1101^2 - 4060^2
+long long busiest_block_work(long long nunits, int ny, long long nb) {
+  const int band = band_of(nunits, ny, nb);
+  const long long total = nunits * ny, band_rows = nunits * band;
+  long long worst = 0;
+  for (long long L = 0; L < nb; ++L) {
+    long long beg = total * L / nb;
+    const long long end = total * (L + 1) / nb;
+    long long work = end - beg;
+    while (beg < end) {
+      const long long b = beg / band_rows, rem = beg - b * band_rows;
+      const long long r0 = b * band, hb = std::min<long long>(band, ny - r0);
+      const long long y0 = r0 + rem % hb;
+      const long long y1 = std::min(r0 + hb, y0 + (end - beg));
+      beg += y1 - y0;
+      work += kPieceWork;
+    }
+    worst = std::max(worst, work);
+  }
+  return worst;
+}
+
 // One block per resident slot (CUs x blocks per CU), so every block runs in
 // a single wave of the grid with an equal share of the unit-rows (a unit is
 // the block's group of neighbouring strips), as long as a share keeps at
 // least 8 unit-rows.  Smaller meshes, where a block's march is a few
 // latency-bound iterations, use one block per CU (equal work on every CU)
 // while a share keeps at least 4 unit-rows, and below that one block per 4
-// unit-rows.  A multiple of 8 for the XCD-aware block order.  Returns the
-// grid size, or -1 if the kernel cannot be resident.
+// unit-rows.  A multiple of 8 for the XCD-aware block order.  Where that
+// count cuts the ranges into many pieces, a count up to a quarter smaller
+// whose busiest block does at least 3% less work (busiest_block_work) is
+// taken instead: a step lasts as long as its busiest block, since with
+// fewer blocks than slots each block marches at about the same rate.
+// Returns the grid size, or -1 if the kernel cannot be resident.
 int plan_blocks(StepParams& p, int storage, int cus) {
   const bool walls = !p.per_x || !p.per_y;
   // Kernel scheme codes: 0 the single-stencil step, 4 the family with
@@ -147,14 +189,26 @@ int plan_blocks(StepParams& p, int storage, int cus) {
   const long long rows = static_cast<long long>(p.nunits) * p.ny;
   const long long slots = static_cast<long long>(cus) * per_cu;
   long long nb = rows >= 8 * slots ? slots : (rows >= 4LL * cus ? cus : rows / 4);
-  if (const char* env = std::getenv("T2S2_BLOCKS")) nb = std::atoll(env);
+  const char* forced = std::getenv("T2S2_BLOCKS");
+  if (forced) nb = std::atoll(forced);
   nb = std::max<long long>(8, nb / 8 * 8);
   nb = std::min<long long>(nb, std::max<long long>(8, rows / 8 * 8));
+  if (!forced) {
+    const long long w0 = busiest_block_work(p.nunits, p.ny, nb);
+    long long best = nb, wbest = w0;
+    for (long long c = nb - 8; c >= std::max<long long>(8, nb - nb / 4); c -= 8) {
+      const long long w = busiest_block_work(p.nunits, p.ny, c);
+      if (w < wbest) {
+        wbest = w;
+        best = c;
+      }
+    }
+    if (wbest * 100 < w0 * 97) nb = best;
+  }
   p.nblocks = static_cast<int>(nb);
-  // Band height = one block's share, so that (away from the last band) each
-  // block owns exactly one unit of one band and the blocks of neighbouring
-  // units march the same rows at the same time.
-  p.band = static_cast<int>(std::min<long long>(p.ny, std::max<long long>(1, (rows + nb - 1) / nb)));
+  // The blocks of neighbouring units in a band march the same rows at the
+  // same time, so the halo lines they share are fetched once.
+  p.band = band_of(p.nunits, p.ny, nb);
   return static_cast<int>(nb);
 }
 

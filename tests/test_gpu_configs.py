@@ -192,6 +192,42 @@ def test_tgv4096_t1s2_vs_t2s2_step_time(storage, monkeypatch):
     _say(f"    tgv4096 {storage}: T2S2-FDLBM1 / T1S2 step-time ratio {us[0.5] / us[0.0]:.3f}")
 
 
+@pytest.mark.parametrize("n", [2812, 4060])
+def test_default_block_count_avoids_split_ranges(n, monkeypatch):
+    """The march's block count on Taylor-Green grids where one block per
+    resident slot (two per CU in FP64) leaves a last band of a few rows, so
+    that each range covering it falls into one piece per unit (2812^2: 52
+    pieces, 4060^2: 74 in the busiest range): the default step time is within
+    10% of the fastest of that count and three counts 8 to 24 below it."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    case = W.tgv_case(n, n, u0=0.01, nu=1e-4, cfl=0.9, eta=0.01, noneq_init=False)
+    us = {}
+    for blocks in (None, 2 * cus, 2 * cus - 8, 2 * cus - 16, 2 * cus - 24):
+        if blocks is None:
+            monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+        else:
+            monkeypatch.setenv("T2S2_BLOCKS", str(blocks))
+        ctx = t2s2.context_for_case(case, storage="f64")
+        ctx.init_macro(case.rho0, case.ux0, case.uy0)
+        ctx.step(20)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.step(50)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        us[blocks] = e0.elapsed_time(e1) / 50 * 1e3
+        assert 0.0 < ctx.diagnostics()["max_speed"] <= 0.01
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+    _say(f"    tgv{n} f64 step time by block count: " +
+         ", ".join(f"{'default' if b is None else b}: {t:.1f} us" for b, t in us.items()))
+    fastest = min(t for b, t in us.items() if b is not None)
+    assert us[None] <= 1.10 * fastest
+
+
 def _cavity257():
     return W.cavity_case(256, lid=0.1, re=1000.0, cfl=0.9, eta=0.1, noise=1e-6, seed=0)
 
