@@ -115,6 +115,30 @@ def test_cavity_ragged_many_tiles(blocks, monkeypatch):
     _compare(case, g, d, u, v, ref)
 
 
+@pytest.mark.parametrize("which", ["tgv1101", "cavity1025"])
+def test_searched_block_count_matches_oracle(which, monkeypatch):
+    """Meshes where one block per resident slot (two per CU in FP64) would
+    cut the ranges covering a short last band into many pieces, so the
+    launch plan takes fewer blocks (1101^2 Taylor-Green: 488; the 1025^2
+    tanh cavity: 480): 6 steps against the oracle on the whole state, and
+    bit for bit the state of one block per slot."""
+    if which == "tgv1101":
+        case = W.tgv_case(1101, 1101, u0=0.01, nu=1e-4, cfl=0.9, eta=0.01)
+        phi0 = oracle.init(case) + W.random_state((9, 1101, 1101), 1e-6, 11)
+    else:
+        case = W.cavity_case(1024, lid=0.1, re=5000.0, cfl=0.9, eta=0.05, noise=1e-6, seed=5)
+        phi0 = oracle.init(case)
+    ref = oracle.run(case, phi0, 6, threads=min(16, os.cpu_count() or 1))
+    monkeypatch.delenv("T2S2_BLOCKS", raising=False)
+    _, g, d, u, v = _gpu_run(case, phi0, 6)
+    _compare(case, g, d, u, v, ref)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    monkeypatch.setenv("T2S2_BLOCKS", str(2 * cus))
+    _, g_slot, _, _, _ = _gpu_run(case, phi0, 6)
+    monkeypatch.delenv("T2S2_BLOCKS")
+    assert np.array_equal(g, g_slot)
+
+
 def test_periodic_tgv_rectangular_multi_strip():
     """Periodic 150x70 Taylor-Green (k1 = 2, k2 = 1), strips wrap across the seam."""
     case = W.tgv_case(150, 70, k1=2.0, k2=1.0, u0=0.02, nu=0.005, cfl=0.7, eta=0.05)
